@@ -1,0 +1,259 @@
+"""ctypes wrapper of the CPU oracle.  TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this module.  It maps a workload dictionary (see ``picinputs``) onto the
+oracle's C configuration and exposes its arrays as numpy views.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc_z", C.c_int32),
+        ("dx_m", C.c_double), ("cfl", C.c_double), ("dt_override", C.c_double),
+        ("gamma_boost", C.c_double), ("window_beta", C.c_double),
+        ("n_beam", C.c_int64),
+        ("charge_C", C.c_double), ("gamma_lab", C.c_double), ("espread", C.c_double),
+        ("sigma", C.c_double * 3), ("emit", C.c_double * 2), ("zc_cells", C.c_double),
+        ("n0_cm3", C.c_double), ("pl_z0_m", C.c_double), ("pl_len_m", C.c_double), ("pl_ramp_m", C.c_double),
+        ("ppc", C.c_int32 * 3), ("ions", C.c_int32),
+        ("und_kind", C.c_int32), ("pusher", C.c_int32),
+        ("K", C.c_double), ("lu_m", C.c_double), ("und_z0_m", C.c_double), ("und_len_m", C.c_double),
+        ("und_ramp_periods", C.c_double),
+        ("hK", C.c_double), ("hn0", C.c_double),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [(n, C.c_double) for n in
+                ("dt", "gR", "bR", "uR", "bw", "nref_m3", "wbeam", "ku", "B0", "n0n", "zoff", "F_elong", "sig_zlab")] + \
+               [(n, C.c_int64) for n in
+                ("k0", "step", "n_beam", "n_plasma", "sheet_lo", "sheet_hi", "beam_lost", "plasma_removed")]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("n_beam_alive", C.c_double), ("wsum", C.c_double),
+                ("mean", C.c_double * 3), ("sigma", C.c_double * 3), ("umean", C.c_double * 3),
+                ("usigma", C.c_double * 3), ("emit", C.c_double * 2),
+                ("b1_re", C.c_double), ("b1_im", C.c_double), ("b2_re", C.c_double), ("b2_im", C.c_double),
+                ("b1_abs", C.c_double), ("b2_abs", C.c_double),
+                ("field_energy", C.c_double), ("kin_beam", C.c_double), ("kin_plasma", C.c_double)]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else float(v)
+        return out
+
+
+_LIBS = {}
+
+
+def lib(complex_step: bool = False):
+    key = bool(complex_step)
+    if key not in _LIBS:
+        path = os.path.join(HERE, "liborc_cs.so" if key else "liborc.so")
+        if not os.path.exists(path):
+            from . import build as _b  # noqa: F401  (oracle/build.py)
+            _b.build()
+        L = C.CDLL(path)
+        R = C.c_void_p
+        L.orc_new.restype = R
+        L.orc_new.argtypes = [C.POINTER(Config), C.c_void_p]
+        L.orc_free.argtypes = [R]
+        L.orc_step.argtypes = [R, C.c_int32]
+        L.orc_info.argtypes = [R, C.POINTER(Info)]
+        L.orc_diag.argtypes = [R, C.c_double, C.POINTER(Diag)]
+        L.orc_field.restype = C.c_void_p
+        L.orc_field.argtypes = [R, C.c_int32]
+        L.orc_particles.restype = C.c_void_p
+        L.orc_particles.argtypes = [R, C.c_int32, C.c_int32]
+        L.orc_alive.restype = C.c_void_p
+        L.orc_alive.argtypes = [R, C.c_int32]
+        L.orc_rho.argtypes = [R, C.c_int32, C.c_void_p]
+        L.orc_gauss.argtypes = [R, C.c_void_p]
+        L.orc_zero_J.argtypes = [R]
+        L.orc_b_half.argtypes = [R]
+        L.orc_e_update.argtypes = [R]
+        L.orc_deposit.argtypes = [R, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_ion_current.argtypes = [R, C.c_double, C.c_double, C.c_int32]
+        L.orc_gather.argtypes = [R, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_push.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        for f in ("orc_beta",):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double]
+        for f in ("orc_elongation", "orc_doppler"):
+            getattr(L, f).restype = C.c_double
+            getattr(L, f).argtypes = [C.c_double, C.c_double]
+        L.orc_fel_wavelength.restype = C.c_double
+        L.orc_fel_wavelength.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_lab_to_boosted.argtypes = [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_state_len.restype = C.c_int64
+        L.orc_state_len.argtypes = [R]
+        L.orc_get_state.argtypes = [R, C.c_void_p]
+        L.orc_set_state.argtypes = [R, C.c_void_p]
+        L.orc_adjoint_step.argtypes = [R, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_grad_bunching.argtypes = [C.POINTER(Config), C.c_void_p, C.c_int32, C.c_double, C.c_void_p]
+        L.orc_loss_bunching.argtypes = [C.POINTER(Config), C.c_void_p, C.c_int32, C.c_double, C.c_void_p]
+        if not key:
+            L.orc_shape.restype = C.c_double
+            L.orc_shape.argtypes = [C.c_double]
+            L.orc_dshape.restype = C.c_double
+            L.orc_dshape.argtypes = [C.c_double]
+        _LIBS[key] = L
+    return _LIBS[key]
+
+
+def make_config(w: dict, *, pusher: int | None = None, bc_z: int = 0, dt_override: float = 0.0,
+                hK: float = 0.0, hn0: float = 0.0) -> Config:
+    g, fr, b, p, u = w["grid"], w["frame"], w["beam"], w["plasma"], w["undulator"]
+    c = Config()
+    c.nx, c.ny, c.nz, c.bc_z = g["nx"], g["ny"], g["nz"], bc_z
+    c.dx_m, c.cfl, c.dt_override = g["dx_m"], g["cfl"], dt_override
+    c.gamma_boost, c.window_beta = fr["gamma_boost"], fr["window_beta"]
+    c.n_beam = b["n_macro"]
+    c.charge_C, c.gamma_lab, c.espread = b["charge_C"], b["gamma_lab"], b["rel_energy_spread_rms"]
+    c.sigma[:] = b["sigma_cells"]
+    c.emit[:] = b["emit_n_m"]
+    c.zc_cells = b["z_center_cells"]
+    c.n0_cm3, c.pl_z0_m, c.pl_len_m, c.pl_ramp_m = p["n0_lab_cm3"], p["z_start_lab_m"], p["length_lab_m"], p["ramp_up_lab_m"]
+    c.ppc[:] = p["ppc"]
+    c.ions = p["ions"]
+    c.und_kind = u["kind"]
+    c.K, c.lu_m, c.und_z0_m, c.und_len_m, c.und_ramp_periods = (u["K"], u["period_lab_m"], u["z_start_lab_m"],
+                                                               u["length_lab_m"], u["entrance_ramp_periods"])
+    c.pusher = (1 if u["kind"] != 0 else 0) if pusher is None else pusher
+    c.hK, c.hn0 = hK, hn0
+    return c
+
+
+FIELD_NAMES = ("Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz")
+
+
+class Sim:
+    """One oracle simulation.  ``complex_step`` selects the complex build."""
+
+    def __init__(self, w: dict, normals: np.ndarray, *, complex_step: bool = False, **cfg_kw):
+        self.L = lib(complex_step)
+        self.cs = complex_step
+        self.dtype = np.complex128 if complex_step else np.float64
+        self.w = w
+        self.cfg = make_config(w, **cfg_kw)
+        self.normals = np.ascontiguousarray(normals, dtype=np.float64)
+        assert self.normals.shape == (6, w["beam"]["n_macro"])
+        self.h = self.L.orc_new(C.byref(self.cfg), self.normals.ctypes.data)
+        if not self.h:
+            raise RuntimeError("orc_new failed")
+
+    def close(self):
+        if self.h:
+            self.L.orc_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        self.L.orc_step(self.h, int(n))
+
+    def info(self) -> Info:
+        i = Info()
+        self.L.orc_info(self.h, C.byref(i))
+        return i
+
+    def diag(self, kb: float) -> dict:
+        d = Diag()
+        self.L.orc_diag(self.h, float(kb), C.byref(d))
+        return d.as_dict()
+
+    @property
+    def nc(self):
+        return self.cfg.nx * self.cfg.ny * self.cfg.nz
+
+    def _view(self, ptr, n, dtype):
+        if n == 0:
+            return np.zeros(0, dtype)
+        buf = (C.c_char * (n * np.dtype(dtype).itemsize)).from_address(ptr)
+        return np.frombuffer(buf, dtype=dtype, count=n)
+
+    def field(self, name) -> np.ndarray:
+        """View (nz, ny, nx) of a field in logical window order."""
+        k = FIELD_NAMES.index(name) if isinstance(name, str) else int(name)
+        v = self._view(self.L.orc_field(self.h, k), self.nc, self.dtype)
+        return v.reshape(self.cfg.nz, self.cfg.ny, self.cfg.nx)
+
+    def particles(self, species: int) -> dict:
+        n = self.info().n_beam if species == 0 else self.info().n_plasma
+        out = {}
+        for k, name in enumerate(("x", "y", "z", "ux", "uy", "uz", "w")):
+            out[name] = self._view(self.L.orc_particles(self.h, species, k), n, self.dtype)
+        out["alive"] = self._view(self.L.orc_alive(self.h, species), n, np.int32)
+        return out
+
+    def rho(self, mask: int = 7) -> np.ndarray:
+        r = np.zeros(self.nc, self.dtype)
+        self.L.orc_rho(self.h, mask, r.ctypes.data)
+        return r.reshape(self.cfg.nz, self.cfg.ny, self.cfg.nx)
+
+    def gauss(self) -> np.ndarray:
+        r = np.zeros(self.nc, self.dtype)
+        self.L.orc_gauss(self.h, r.ctypes.data)
+        return r.reshape(self.cfg.nz, self.cfg.ny, self.cfg.nx)
+
+    def state(self) -> np.ndarray:
+        v = np.zeros(self.L.orc_state_len(self.h), self.dtype)
+        self.L.orc_get_state(self.h, v.ctypes.data)
+        return v
+
+    def set_state(self, v: np.ndarray):
+        v = np.ascontiguousarray(v, dtype=self.dtype)
+        assert v.size == self.L.orc_state_len(self.h)
+        self.L.orc_set_state(self.h, v.ctypes.data)
+
+    def adjoint_step(self, lam_in: np.ndarray, n_out: int):
+        lam_in = np.ascontiguousarray(lam_in, dtype=self.dtype)
+        out = np.zeros(n_out, self.dtype)
+        gK = np.zeros(1, self.dtype)
+        gn = np.zeros(1, self.dtype)
+        self.L.orc_adjoint_step(self.h, lam_in.ctypes.data, out.ctypes.data, gK.ctypes.data, gn.ctypes.data)
+        return out, gK[0], gn[0]
+
+
+def grad_bunching(w: dict, normals: np.ndarray, nsteps: int, kb: float, **cfg_kw):
+    """(L, K dL/dK, n0 dL/dn0) from the oracle's stored-state adjoint."""
+    L = lib(False)
+    cfg = make_config(w, **cfg_kw)
+    nrm = np.ascontiguousarray(normals, dtype=np.float64)
+    out = np.zeros(3)
+    L.orc_grad_bunching(C.byref(cfg), nrm.ctypes.data, int(nsteps), float(kb), out.ctypes.data)
+    return out
+
+
+def loss_bunching(w: dict, normals: np.ndarray, nsteps: int, kb: float, *, complex_step=False, **cfg_kw):
+    L = lib(complex_step)
+    cfg = make_config(w, **cfg_kw)
+    nrm = np.ascontiguousarray(normals, dtype=np.float64)
+    out = np.zeros(2)
+    L.orc_loss_bunching(C.byref(cfg), nrm.ctypes.data, int(nsteps), float(kb), out.ctypes.data)
+    return out
+
+
+def push(pusher: int, qm: float, dt: float, u, E, B):
+    L = lib(False)
+    u = np.ascontiguousarray(u, np.float64)
+    E = np.ascontiguousarray(E, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    out = np.zeros(3)
+    L.orc_push(pusher, qm, dt, u.ctypes.data, E.ctypes.data, B.ctypes.data, out.ctypes.data)
+    return out

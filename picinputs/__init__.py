@@ -1,0 +1,153 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle harness.
+
+This module holds workload *data* only: grid sizes, species parameters in
+physical units, seeds, and the standard-normal draws a beam is sampled from.
+It contains none of the simulation's arithmetic (no frame transform, no unit
+conversion, no field or particle update); both the HIP library and the CPU
+oracle take these numbers and derive everything themselves.
+
+Workloads
+---------
+The five workloads are 3D stand-ins for the paper's 2D runs (Table 1 of the
+paper, cases V., Und., Pl., Pl.+Und.).  Their sizes come from the build's
+hot-path specification; every choice the paper leaves open is recorded next
+to the field it fixes:
+
+* cell edge: a quarter of the plasma skin depth c/omega_p at 1e16 cm^-3,
+  13.285 um, for every workload;
+* beam charge 30 pC, as in the paper's runs (section 3);
+* beam rms sizes: transverse in cells (frame invariant), longitudinal in
+  boosted-frame cells (after the frame change);
+* 0.1 % rms energy spread, 1 um normalised emittance in x and y;
+* undulator period 20 boosted-frame cells, i.e. 20*gamma_R cells in the lab,
+  entrance one lab period ahead of the beam head, two-period linear ramp;
+* plasma lattice (1,1,2) for 2 particles per cell and (1,2,2) for 4.
+
+Lab-frame longitudinal positions (undulator start, plasma start) are measured
+from the beam centre at lab time 0.
+"""
+from __future__ import annotations
+
+import copy
+import numpy as np
+
+DX_M = 13.285e-6          # cell edge: (c/omega_p at 1e16 cm^-3) / 4
+Q_BEAM_C = 30e-12         # beam charge (paper, section 3)
+
+
+def _undulator_start_m(gamma_r: float, sigma_z_cells: float, period_cells_boosted: float) -> float:
+    """Lab position of the undulator entrance: one lab period ahead of the beam head (3 sigma).
+
+    Pure bookkeeping of where the element sits; lengths in cells times the cell edge.
+    """
+    head_lab_cells = gamma_r * 3.0 * sigma_z_cells
+    period_lab_cells = gamma_r * period_cells_boosted
+    return (head_lab_cells + period_lab_cells) * DX_M
+
+
+def _base(nx, ny, nz, gamma_r, n_beam, sigma, steps):
+    return {
+        "grid": {"nx": nx, "ny": ny, "nz": nz, "dx_m": DX_M, "cfl": 0.95},
+        "frame": {"gamma_boost": float(gamma_r), "window_beta": -1.0},
+        "beam": {"n_macro": int(n_beam), "charge_C": Q_BEAM_C, "gamma_lab": 200.0,
+                 "rel_energy_spread_rms": 1e-3, "sigma_cells": [float(s) for s in sigma],
+                 "emit_n_m": [1e-6, 1e-6], "z_center_cells": nz // 2, "seed": 0},
+        "plasma": {"n0_lab_cm3": 0.0, "ppc": [1, 1, 2], "z_start_lab_m": 0.0,
+                   "length_lab_m": 0.0, "ramp_up_lab_m": 0.0, "ions": 0},
+        "undulator": {"kind": 0, "K": 0.0, "period_lab_m": 0.0, "z_start_lab_m": 0.0,
+                      "length_lab_m": 0.0, "entrance_ramp_periods": 0.0},
+        "steps": int(steps),
+        "bunch_period_cells": 20.0,
+    }
+
+
+def _with_undulator(w, K=1.0, length_m=1.0):
+    g = w["frame"]["gamma_boost"]
+    period_lab_m = 20.0 * g * DX_M
+    w["undulator"] = {"kind": 1, "K": float(K), "period_lab_m": period_lab_m,
+                      "z_start_lab_m": _undulator_start_m(g, w["beam"]["sigma_cells"][2], 20.0),
+                      "length_lab_m": float(length_m), "entrance_ramp_periods": 2.0}
+    return w
+
+
+def _with_plasma(w, n0_cm3, ppc, uniform=True, z_start_m=0.0, length_m=0.0, ramp_m=0.0):
+    w["plasma"] = {"n0_lab_cm3": float(n0_cm3), "ppc": list(ppc),
+                   "z_start_lab_m": float(z_start_m),
+                   "length_lab_m": 0.0 if uniform else float(length_m),
+                   "ramp_up_lab_m": float(ramp_m), "ions": 1}
+    return w
+
+
+def workload(idx: int) -> dict:
+    """The five hot-path workloads, 0..4."""
+    if idx == 0:
+        # FP64 parity case: beam in a helical undulator, no plasma.
+        w = _base(32, 32, 64, 10.0, 16_384, (4, 4, 8), 100)
+        return _with_undulator(w, K=1.0)
+    if idx == 1:
+        # FP64 vs FP32: beam plus uniform cold plasma (2 ppc) with immobile ions.
+        w = _base(128, 128, 512, 20.0, 4_194_304, (4, 4, 32), 1000)
+        return _with_plasma(w, 1e16, (1, 1, 2))
+    if idx == 2:
+        # Split precision at scale: 4 ppc plasma channel, 10 cm long, 1 cm up-ramp,
+        # starting just ahead of the window front (lab).
+        w = _base(256, 256, 1024, 20.0, 16_777_216, (4, 4, 32), 5000)
+        front_lab_m = 20.0 * (1024 - 512) * DX_M
+        return _with_plasma(w, 1e16, (1, 2, 2), uniform=False,
+                            z_start_m=front_lab_m + 20.0 * 8 * DX_M, length_m=0.10, ramp_m=0.01)
+    if idx == 3:
+        # Adjoint case: beam, undulator (K in [0.5, 2]) and plasma (1e15..1e17 cm^-3).
+        w = _base(64, 64, 256, 10.0, 1_048_576, (4, 4, 16), 500)
+        w = _with_undulator(w, K=1.0)
+        w = _with_plasma(w, 1e16, (1, 1, 2))
+        w["checkpoint_every"] = 50
+        return w
+    if idx == 4:
+        # Largest single-GPU run: undulator plus plasma pre-buncher at gamma_R = 40.
+        w = _base(512, 512, 2048, 40.0, 33_554_432, (4, 4, 32), 20000)
+        w = _with_undulator(w, K=1.0, length_m=2.0)
+        return _with_plasma(w, 1e16, (1, 1, 2))
+    raise ValueError(idx)
+
+
+def adjoint_subcase() -> dict:
+    """16x16x64 reduction of workload 3 on which the oracle's adjoint is affordable."""
+    w = _base(16, 16, 64, 10.0, 16_384, (2, 2, 8), 500)
+    w = _with_undulator(w, K=1.0)
+    w = _with_plasma(w, 1e16, (1, 1, 2))
+    w["checkpoint_every"] = 50
+    return w
+
+
+def scaled(w: dict, *, nx=None, ny=None, nz=None, n_beam=None, steps=None, sigma=None) -> dict:
+    """Copy of a workload with a smaller grid / beam (for oracle-sized parity cases)."""
+    w = copy.deepcopy(w)
+    if nx is not None:
+        w["grid"]["nx"] = nx
+    if ny is not None:
+        w["grid"]["ny"] = ny
+    if nz is not None:
+        w["grid"]["nz"] = nz
+        w["beam"]["z_center_cells"] = nz // 2
+    if n_beam is not None:
+        w["beam"]["n_macro"] = int(n_beam)
+    if steps is not None:
+        w["steps"] = int(steps)
+    if sigma is not None:
+        w["beam"]["sigma_cells"] = [float(s) for s in sigma]
+    return w
+
+
+def beam_normals(n: int, seed: int = 0) -> np.ndarray:
+    """Standard-normal draws for a beam of n macroparticles, shape (6, n), float64, C order.
+
+    Rows: x, y, z, ux, uy, energy.  Both implementations turn these into a
+    lab-frame Gaussian beam with their own arithmetic.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x5EED]))
+    return np.ascontiguousarray(rng.standard_normal((6, int(n))))
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    """A seeded random permutation (for order-independence tests)."""
+    return np.random.default_rng(seed).permutation(n)

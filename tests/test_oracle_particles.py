@@ -1,0 +1,319 @@
+"""Oracle pins for shapes, gather, pushers, Esirkepov deposition, ion sheet,
+plasma loading and injection, Gauss law, cold-plasma frequency, bunching
+factor and ballistic expansion (sec. 1 and 3 of the paper; closed forms)."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import picinputs as pin
+from oracle import pyoracle as po
+
+pytestmark = pytest.mark.usefixtures("oracle_built")
+
+
+def S(d):
+    return po.lib().orc_shape(float(d))
+
+
+def test_quadratic_spline_values_and_moments():
+    L = po.lib()
+    assert S(0) == 0.75 and S(0.5) == 0.5 and S(-0.5) == 0.5
+    assert S(1.0) == 0.125 and S(-1.0) == 0.125 and S(1.5) == 0.0 and S(-1.6) == 0.0
+    rng = np.random.default_rng(0)
+    for x in rng.uniform(-3, 3, 200):
+        nodes = np.arange(math.floor(x) - 3, math.floor(x) + 4)
+        w = np.array([S(x - n) for n in nodes])
+        assert abs(w.sum() - 1) < 1e-15
+        assert abs((w * nodes).sum() - x) < 1e-13
+        assert abs((w * (nodes - x) ** 2).sum() - 0.25) < 1e-13  # variance of the quadratic B-spline
+        h = 1e-6
+        assert abs((S(x + h) - S(x - h)) / (2 * h) - L.orc_dshape(float(x))) < 1e-8
+
+
+def _sim(nx=8, ny=8, nz=16, n_beam=0, plasma=None, und=False, bc_z=1, gR=10.0, **kw):
+    w = pin.scaled(pin.workload(0), nx=nx, ny=ny, nz=nz, n_beam=n_beam)
+    w["frame"]["gamma_boost"] = gR
+    if not und:
+        w["undulator"]["kind"] = 0
+    if plasma:
+        w["plasma"].update(n0_lab_cm3=plasma.get("n0", 1e16), ppc=plasma.get("ppc", [1, 1, 2]), ions=1,
+                           length_lab_m=plasma.get("len", 0.0), z_start_lab_m=plasma.get("z0", 0.0),
+                           ramp_up_lab_m=plasma.get("ramp", 0.0))
+    return po.Sim(w, pin.beam_normals(n_beam), bc_z=bc_z, **kw)
+
+
+def _vec(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def test_gather_reproduces_linear_fields():
+    s = _sim(16, 16, 16)
+    a, b = 0.3, np.array([0.11, -0.07, 0.05])
+    stag = {"Ex": (0.5, 0, 0), "Ey": (0, 0.5, 0), "Ez": (0, 0, 0.5),
+            "Bx": (0, 0.5, 0.5), "By": (0.5, 0, 0.5), "Bz": (0.5, 0.5, 0)}
+    kk, jj, ii = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
+    for k, (ox, oy, oz) in enumerate(stag.values()):
+        s.field(list(stag)[k])[:] = a + k + b[0] * (ii + ox) + b[1] * (jj + oy) + b[2] * (kk + oz)
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        X = _vec(rng.uniform(4, 11, 3))
+        E = np.zeros(3)
+        B = np.zeros(3)
+        s.L.orc_gather(s.h, X.ctypes.data, E.ctypes.data, B.ctypes.data)
+        got = np.concatenate([E, B])
+        want = np.array([a + k + b @ X for k in range(6)])
+        np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+def test_boris_gyration_angle_and_energy():
+    """Uniform B: |u| is conserved and the rotation per step is 2 atan(Omega dt / (2 gamma))."""
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        u = rng.normal(size=3) * rng.uniform(0.1, 30)
+        Bv = rng.normal(size=3)
+        dt = rng.uniform(0.1, 0.9)
+        out = po.push(0, -1.0, dt, u, np.zeros(3), Bv)
+        g = math.sqrt(1 + u @ u)
+        assert abs(math.sqrt(out @ out) - math.sqrt(u @ u)) < 1e-13 * math.sqrt(u @ u)
+        bh = Bv / np.linalg.norm(Bv)
+        up, op = u - (u @ bh) * bh, out - (out @ bh) * bh
+        ang = math.atan2(np.linalg.norm(np.cross(up, op)), up @ op)
+        assert abs(ang - 2 * math.atan(np.linalg.norm(Bv) * dt / (2 * g))) < 1e-12
+        # electron (q/m = -1) rotates right-handed about B
+        assert np.cross(up, op) @ bh > 0
+
+
+@pytest.mark.parametrize("pusher", [0, 1])
+def test_uniform_electric_field_exact(pusher):
+    u = np.array([0.3, -1.2, 4.0])
+    E = np.array([0.01, 0.02, -0.03])
+    dt = 0.5
+    for n in range(1, 6):
+        u = po.push(pusher, -1.0, dt, u, E, np.zeros(3))
+    np.testing.assert_allclose(u, np.array([0.3, -1.2, 4.0]) - 5 * dt * E, atol=1e-14)
+
+
+def test_vay_conserves_u_magnitude_in_pure_b():
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        u = rng.normal(size=3) * 10
+        out = po.push(1, -1.0, 0.5, u, np.zeros(3), rng.normal(size=3))
+        assert abs(np.linalg.norm(out) - np.linalg.norm(u)) < 1e-13 * np.linalg.norm(u)
+
+
+def _deposit(s, X0, X1, qw):
+    s.L.orc_deposit.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]
+    a, b = _vec(X0), _vec(X1)  # keep the buffers alive across the call
+    s.L.orc_deposit(s.h, a.ctypes.data, b.ctypes.data, float(qw))
+
+
+def _rho_point(s, X, qw, shape):
+    nz, ny, nx = shape
+    r = np.zeros(shape)
+    lo = [math.floor(X[d] + 0.5) - 1 for d in range(3)]
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                i, j, k = lo[0] + a, lo[1] + b, lo[2] + c
+                r[k % nz, j % ny, i % nx] += qw * S(X[0] - i) * S(X[1] - j) * S(X[2] - k)
+    return r
+
+
+def test_esirkepov_discrete_continuity_and_current_sum():
+    """(rho1 - rho0)/dt + div J = 0 on every node to round-off; sum J_c = q w dX_c / dt."""
+    nx, ny, nz = 8, 8, 8
+    s = _sim(nx, ny, nz)
+    dt = s.info().dt
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        s.L.orc_zero_J(s.h)
+        X0 = rng.uniform(0, 8, 3)
+        dX = rng.uniform(-0.55, 0.55, 3)
+        X1 = X0 + dX
+        qw = rng.uniform(-2, 2)
+        _deposit(s, X0, X1, qw)
+        Jx, Jy, Jz = s.field("Jx"), s.field("Jy"), s.field("Jz")
+        divJ = (Jx - np.roll(Jx, 1, 2)) + (Jy - np.roll(Jy, 1, 1)) + (Jz - np.roll(Jz, 1, 0))
+        dr = _rho_point(s, X1, qw, (nz, ny, nx)) - _rho_point(s, X0, qw, (nz, ny, nx))
+        assert np.abs(dr / dt + divJ).max() < 1e-13 * max(1, abs(qw) / dt)
+        for c, J in enumerate((Jx, Jy, Jz)):
+            assert abs(J.sum() - qw * dX[c] / dt) < 1e-13 * abs(qw) / dt
+
+
+def test_esirkepov_1d_move_is_unique_running_sum():
+    nx, ny, nz = 4, 4, 16
+    s = _sim(nx, ny, nz)
+    dt = s.info().dt
+    s.L.orc_zero_J(s.h)
+    X0 = np.array([1.3, 2.1, 7.2])
+    X1 = X0 + np.array([0.0, 0.0, -0.41])
+    _deposit(s, X0, X1, -1.0)
+    assert np.abs(s.field("Jx")).max() == 0 and np.abs(s.field("Jy")).max() == 0
+    dr = _rho_point(s, X1, -1.0, (nz, ny, nx)) - _rho_point(s, X0, -1.0, (nz, ny, nx))
+    # J_z(k+1/2) = -sum_{k' <= k} drho(k') / dt
+    np.testing.assert_allclose(s.field("Jz"), -np.cumsum(dr, axis=0) / dt, atol=1e-14)
+
+
+def test_ion_sheet_equals_brute_force_lattice_deposit():
+    s = _sim(4, 4, 16, plasma={"ppc": [1, 2, 2]})
+    i = s.info()
+    dt = i.dt
+    t0, t1 = 3 * dt, 4 * dt
+    s.L.orc_zero_J(s.h)
+    s.L.orc_ion_current(s.h, t0, t1, 0)
+    J_sheet = [s.field(c).copy() for c in ("Jx", "Jy", "Jz")]
+    s.L.orc_zero_J(s.h)
+    ppc = [1, 2, 2]
+    w = s.particles(1)["w"][0]  # uniform plasma: every lattice particle carries the same weight
+    for l in range(i.sheet_lo, i.sheet_hi):
+        z0 = (l + 0.5) / ppc[2] - i.bR * t0
+        z1 = (l + 0.5) / ppc[2] - i.bR * t1
+        for jj in range(4):
+            for b in range(ppc[1]):
+                for ii in range(4):
+                    for a in range(ppc[0]):
+                        x, y = ii + (a + 0.5) / ppc[0], jj + (b + 0.5) / ppc[1]
+                        _deposit(s, [x, y, z0], [x, y, z1], +w)
+    for c, name in enumerate(("Jx", "Jy", "Jz")):
+        np.testing.assert_allclose(J_sheet[c], s.field(name), atol=1e-12 * abs(J_sheet[2]).max())
+
+
+def test_plasma_loading_density_is_gamma_n_and_neutral():
+    """Eq. Nnormi: the boosted-frame density is gamma_R n; electrons + ions cancel exactly."""
+    s = _sim(4, 4, 48, plasma={"ppc": [1, 1, 2]}, bc_z=0, gR=20.0)
+    i = s.info()
+    rho_e = s.rho(2)
+    rho_net = s.rho(6)
+    inner = slice(6, 48 - 7)
+    np.testing.assert_allclose(rho_e[inner], -i.gR * i.n0n, rtol=1e-13)
+    assert np.abs(rho_net[inner]).max() < 1e-13 * i.gR * i.n0n
+    p = s.particles(1)
+    np.testing.assert_allclose(p["uz"], -i.uR, rtol=0)
+
+
+@pytest.mark.parametrize("gR,lab_m,boosted_m", [(10.0, 0.20, 20e-3), (25.0, 0.20, 8e-3)])
+def test_plasma_column_contracts_by_gamma(gR, lab_m, boosted_m):
+    """Table 1: a lab plasma of length L occupies L / gamma_R in the boosted frame."""
+    dx = 0.1e-3
+    nz = 256
+    w = pin.scaled(pin.workload(0), nx=2, ny=2, nz=nz, n_beam=0)
+    w["grid"]["dx_m"] = dx
+    w["frame"].update(gamma_boost=gR, window_beta=0.0)
+    w["undulator"]["kind"] = 0
+    w["beam"]["z_center_cells"] = 128
+    w["plasma"].update(n0_lab_cm3=1e16, ppc=[1, 1, 2], ions=1, length_lab_m=lab_m,
+                       z_start_lab_m=gR * (10 - 128) * dx, ramp_up_lab_m=0.0)
+    s = po.Sim(w, pin.beam_normals(0))
+    p = s.particles(1)
+    length_cells = (p["z"].max() - p["z"].min()) + 0.5  # sheet spacing 1/2
+    assert abs(length_cells * dx - boosted_m) <= 0.5 * dx + 1e-3 * boosted_m
+
+
+def test_window_follows_beam_and_plasma_stays_uniform():
+    s = _sim(4, 4, 48, n_beam=0, plasma={"ppc": [1, 1, 2]}, bc_z=0, gR=20.0)
+    s.cfg  # noqa
+    w = s.w
+    w["frame"]["window_beta"] = 0.98
+    s = po.Sim(w, pin.beam_normals(0), bc_z=0)
+    i0 = s.info()
+    N = 40
+    s.step(N)
+    i = s.info()
+    assert i.k0 == math.floor(0.98 * N * i.dt)
+    rho_e = s.rho(2)
+    inner = slice(7, 48 - 8)
+    np.testing.assert_allclose(rho_e[inner], -i.gR * i.n0n, rtol=1e-12)
+    p = s.particles(1)
+    alive = p["alive"] == 1
+    assert abs(alive.sum() - (i0.n_plasma)) <= 4 * 4 * 2 * 2  # count stays within a sheet pair
+    z = p["z"][alive]
+    assert z.min() >= i.k0 + 3 and z.max() < i.k0 + 48 - 4
+
+
+def _aligned_residuals(s, n_steps):
+    out = []
+    r_prev, k_prev = s.gauss().copy(), s.info().k0
+    for _ in range(n_steps):
+        s.step(1)
+        r, k = s.gauss().copy(), s.info().k0
+        sh = k - k_prev
+        a = r_prev[sh:] if sh else r_prev
+        b = r[: r.shape[0] - sh] if sh else r
+        out.append(np.abs(b[8:-9] - a[8:-9]).max())
+        r_prev, k_prev = r, k
+    return out
+
+
+def test_gauss_law_residual_is_invariant():
+    """div E - rho changes only by round-off per step away from the faces (charge conservation)."""
+    w = pin.scaled(pin.workload(3), nx=8, ny=8, nz=48, n_beam=2048, sigma=(2, 2, 6))
+    w["beam"]["charge_C"] = 3e-9  # strong self fields, so the test is not trivial
+    s = po.Sim(w, pin.beam_normals(2048, 1))
+    rho_scale = np.abs(s.rho(7)).max() + np.abs(s.rho(1)).max()
+    res = _aligned_residuals(s, 30)
+    assert max(res) < 1e-12 * rho_scale, res
+    assert np.abs(s.field("Ex")).max() > 1e-6  # fields were actually driven
+
+
+def test_cold_plasma_frequency_is_frame_invariant():
+    """Uniform transverse oscillation of a plasma drifting at -beta_R: the leap-frog
+    orbit satisfies u^{n+3/2} + u^{n-1/2} = 2 cos(theta) u^{n+1/2} with
+    sin(theta/2) = omega_p dt / 2, omega_p^2 = n_lab / n_ref, independent of gamma_R."""
+    for gR in (1.0001, 5.0, 20.0):
+        s = _sim(2, 2, 8, plasma={"ppc": [1, 1, 2]}, gR=gR)
+        i = s.info()
+        p = s.particles(1)
+        A = 1e-6
+        p["ux"][:] = A
+        us = []
+        for _ in range(12):
+            us.append(p["ux"].mean())
+            s.step(1)
+        us = np.array(us)
+        cos_th = (us[2:] + us[:-2]) / (2 * us[1:-1])
+        wp = math.sqrt(i.n0n)
+        expect = 1 - 2 * (wp * i.dt / 2) ** 2
+        np.testing.assert_allclose(cos_th, expect, atol=1e-9)
+
+
+def test_bunching_factor_lattice_and_uniform():
+    s = _sim(8, 8, 64, n_beam=4096, bc_z=1)
+    p = s.particles(0)
+    rng = np.random.default_rng(9)
+    p["z"][:] = 5.0 + 20.0 * rng.integers(0, 3, p["z"].size)
+    p["alive"][:] = 1
+    d = s.diag(2 * math.pi / 20)
+    assert abs(d["b1_abs"] - 1) < 1e-12 and abs(d["b2_abs"] - 1) < 1e-12
+    p["z"][:] = rng.uniform(0, 60, p["z"].size)
+    d = s.diag(2 * math.pi / 20)
+    assert d["b1_abs"] < 4 / math.sqrt(p["z"].size)
+
+
+def test_vacuum_ballistic_expansion_matches_lab_closed_form():
+    """Fields off, negligible charge: the rms size follows the lab-frame drift
+    sigma^2(s) = sigma0^2 + 2 <x x'> s + <x'^2> s^2 (x' = u_x / gamma_B) in the lab
+    distance s, which the boosted run covers at s = beta_B t' / (gamma_R (1 - beta_R beta_B))."""
+    w = pin.scaled(pin.workload(0), nx=64, ny=64, nz=64, n_beam=20000)
+    w["undulator"]["kind"] = 0
+    w["beam"]["charge_C"] = 1e-30
+    w["beam"]["emit_n_m"] = [1e-5, 1e-5]
+    w["beam"]["rel_energy_spread_rms"] = 0.0
+    s = po.Sim(w, pin.beam_normals(20000, 11))
+    i = s.info()
+    p = s.particles(0)
+    al = p["alive"] == 1
+    x0 = {k: p[k][al].copy() for k in ("x", "y", "ux", "uy")}
+    N = 150
+    s.step(N)
+    d1 = s.diag(1.0)
+    gB, gR = w["beam"]["gamma_lab"], i.gR
+    bB = math.sqrt(1 - 1 / gB ** 2)
+    sdist = bB * N * i.dt / (gR * (1 - i.bR * bB))
+    for k, (xn, un) in enumerate((("x", "ux"), ("y", "uy"))):
+        dx = x0[xn] - x0[xn].mean()
+        du = (x0[un] - x0[un].mean()) / gB
+        pred = math.sqrt((dx @ dx + 2 * (dx @ du) * sdist + (du @ du) * sdist ** 2) / dx.size)
+        assert abs(d1["sigma"][k] - pred) < 1e-3 * pred, (k, d1["sigma"][k], pred)
+    assert d1["sigma"][0] > 1.05 * math.sqrt((x0["x"].var()))  # the beam did expand
