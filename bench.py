@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark of the boosted-frame PIC hot path on one MI355X.
+
+One step = gather, push, current deposition (all particles), ion current,
+Yee FDTD, window shift and plasma injection, on the 128x128x512 workload
+(gamma_R = 20, 4,194,304-particle beam plus 2 ppc cold plasma with immobile
+ions).  Prints one JSON line: whole-job particle-steps/s, FDTD
+cell-updates/s, the roofline fraction of the dominant (particle) kernel
+measured with HIP events on the library's stream, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s and FDTD cell-updates/s; FP32 vs FP64 speedup at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(precision: int, n_particles: float, n_cells: int) -> dict:
+    """Bytes the particle phase must move per step: each particle's state read
+    and written once, the fields it gathers read once, the current written once."""
+    if precision == 1:  # FP32 split: cell int32 + 3 offsets + 3 momenta + weight read; all but weight written
+        per_p, per_c = 32 + 28, 24 + 24  # E,B float read; J int64 written
+    else:  # FP64 plain: 7 doubles read, 6 written; E,B double read, J double written
+        per_p, per_c = 56 + 48, 48 + 24
+    return {"per_particle": per_p, "per_cell": per_c, "total": per_p * n_particles + per_c * n_cells}
+
+
+def cpu_baseline(seconds_budget: float = 20.0) -> dict:
+    """The oracle, single-threaded FP64, on 1/64 of the workload's volume (same densities)."""
+    import numpy as np  # noqa: F401
+    import picinputs as pin
+    from oracle import build as ob
+    from oracle import pyoracle as po
+
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
+        ob.build()
+    w = pin.scaled(pin.workload(1), nx=32, ny=32, nz=128, n_beam=4_194_304 // 64, sigma=(4, 4, 8))
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
+    s = po.Sim(w, nrm)
+    i = s.info()
+    npart = i.n_beam + i.n_plasma
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        s.step(1)
+        steps += 1
+        if time.perf_counter() - t0 > seconds_budget / 2 or steps >= 20:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": npart * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"32x32x128 cells (1/64 of the workload volume), {i.n_beam} beam + {i.n_plasma} plasma "
+                      f"particles, {steps} steps, single-threaded FP64 C"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path (speedup and error)")
+    ap.add_argument("--variant", type=int, default=0, help="FP32 particle-kernel launch shape (0 or 1)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import picinputs as pin
+    from paper_2411_04703_amd import abi
+    from paper_2411_04703_amd.sim import Sim
+
+    w = pin.workload(1)
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
+    g = w["grid"]
+    n_cells = g["nx"] * g["ny"] * g["nz"]
+
+    def run(precision):
+        opts = dict(precision=precision)
+        if precision == abi.PIC_FP32_SPLIT:
+            opts["variant"] = args.variant
+        if precision == abi.PIC_FP64_PLAIN:
+            opts["max_steps"] = 64
+        sim = Sim(w, nrm, **opts)
+        sim.step(args.warmup)
+        d0 = sim.diag(abi.PIC_DIAG_MOMENTS)
+        sim.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, launches = sim.timing_read()
+        sim.timing(False)
+        d1 = sim.diag(abi.PIC_DIAG_MOMENTS | abi.PIC_DIAG_BUNCHING)
+        n_active = 0.5 * ((d0["n_beam"] + d0["n_plasma"]) + (d1["n_beam"] + d1["n_plasma"]))
+        del sim
+        torch.cuda.empty_cache()
+        return wall, ms, launches, n_active, d1
+
+    prec = abi.PIC_FP32_SPLIT if args.precision == "fp32" else abi.PIC_FP64_PLAIN
+    wall, ms, launches, n_active, dlast = run(prec)
+    steps = args.steps
+    ps = n_active * steps / wall
+    fdtd_ms = ms[1] / steps
+    part_ms = ms[0] / steps
+    ab = algorithmic_bytes(prec, n_active, n_cells)
+    achieved = ab["total"] / (part_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": ps,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == abi.PIC_FP32_SPLIT else "f64",
+        "data": "synthetic",
+        "config": {"workload": "128x128x512 cells, gamma_R=20, beam 4,194,304 macroparticles (sigma 4x4x32 cells, "
+                               "lab gamma 200) + cold plasma 1e16 cm^-3 at 2 ppc with immobile ions",
+                   "particles_active": n_active, "cells": n_cells,
+                   "precision": "fp32_split_fixed_point" if prec == abi.PIC_FP32_SPLIT else "fp64_plain",
+                   "kernel_variant": args.variant},
+        "fdtd_cell_updates_per_s": n_cells / (fdtd_ms * 1e-3) if fdtd_ms > 0 else None,
+        "phase_ms_per_step": {"particles": part_ms, "fdtd": fdtd_ms, "window_ion_inject_sort": ms[2] / steps,
+                              "step_events": ms[3] / steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fused particle kernel(s): gather, push, deposit",
+                     "bytes_per_step": ab["total"], "bytes_per_particle": ab["per_particle"],
+                     "bytes_per_cell": ab["per_cell"], "avg_ms_per_step": part_ms,
+                     "launches": launches[0]},
+        "beam_end": {"sigma": dlast["sigma"], "b1_abs": dlast["b1_abs"], "emit": dlast["emit"]},
+    }
+    if not args.no_fp64 and prec != abi.PIC_FP64_PLAIN:
+        w64, ms64, _, na64, d64 = run(abi.PIC_FP64_PLAIN)
+        ps64 = na64 * steps / w64
+        out["fp64_particle_steps_per_s"] = ps64
+        out["fp64_ms_per_step"] = w64 / steps * 1e3
+        out["fp32_vs_fp64_speedup"] = ps / ps64
+        # error of the FP32 path at the same step, against the FP64 GPU path
+        rel = {}
+        for k in ("mean", "sigma", "usigma", "emit"):
+            a, b = dlast[k], d64[k]
+            rel[k] = max(abs(x - y) / max(abs(y), 1e-300) for x, y in zip(a, b))
+        rel["b1_abs_abs"] = abs(dlast["b1_abs"] - d64["b1_abs"])
+        out["fp32_vs_fp64_error"] = rel
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * pic.h -- C-ABI of the MI355X boosted-frame PIC hot path.
+ *
+ * The library advances an electron beam (and optionally a cold plasma with
+ * immobile ions, and an external undulator field) in a reference frame that
+ * moves with Lorentz factor gamma_R along +z, following the method of
+ * "Relativistic reference frame PIC simulations for electron beam dynamics
+ * with meter-scale propagation inside plasma and under external fields":
+ * Maxwell's curl equations with electron and ion currents (section 1,
+ * Eq. Max1, Max2) on a Yee grid, charge-conserving current weighting
+ * (Eq. Max3, Max4; Esirkepov's scheme with quadratic shapes), a leap-frog
+ * relativistic push (section 1, after Eq. Vprime), the beam, field and
+ * density transforms of section 1 (Eq. Lor1-Belon, M1-M4, Nnormi, Vprime)
+ * and a moving window with absorbing z faces and plasma streaming through it
+ * (end of section 1).
+ *
+ * Conventions
+ *   - Units: all arguments are physical SI (m, C, T via K) or dimensionless;
+ *     internally length = cell edge D, time = D/c, u = gamma*beta.
+ *   - Memory: the caller owns all device memory.  pic_query_layout() reports
+ *     how many bytes the context needs; the caller allocates ONE device
+ *     buffer of at least that size (256-byte aligned) and passes it to
+ *     pic_init(), which borrows it until pic_free().  The context allocates
+ *     no device memory of its own and never frees caller memory.
+ *   - Streams: every launch goes to options.stream (a hipStream_t, NULL for
+ *     the null stream).  pic_step() is asynchronous; pic_diag(), pic_read(),
+ *     pic_get_state() and pic_sync() synchronise the stream.
+ *   - Errors: functions return pic_status; no exception or abort crosses the
+ *     ABI.  pic_last_error() returns a context-owned message.  Device-side
+ *     error flags (fixed-point overflow, non-finite momentum, bin overflow
+ *     without room) are raised at the next synchronising call.
+ *   - Threads: one context per host thread; a context is not re-entrant.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PIC_API __attribute__((visibility("default")))
+#else
+#define PIC_API
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,  /* invalid argument or configuration */
+    PIC_ENOMEM = -2,  /* caller buffer too small / capacity exceeded */
+    PIC_EDEVICE = -3, /* HIP runtime error */
+    PIC_ESTATE = -4,  /* non-finite state detected, or call not valid in this state */
+    PIC_ERANGE = -5   /* fixed-point current overflow */
+} pic_status;
+
+enum { PIC_FP64_PLAIN = 0, PIC_FP32_SPLIT = 1 };
+enum { PIC_BORIS = 0, PIC_VAY = 1, PIC_PUSHER_AUTO = -1 };
+enum { PIC_UND_NONE = 0, PIC_UND_HELICAL = 1, PIC_UND_PLANAR = 2 };
+
+/* Boosted-frame grid: nx x ny x nz cubic cells of edge dx_m; x, y periodic,
+ * z open (first-order Mur faces) with a moving window.  dt = cfl dx / (c sqrt 3). */
+typedef struct {
+    int32_t nx, ny, nz, reserved;
+    double dx_m, cfl;
+} pic_grid;
+
+/* gamma_boost: Lorentz factor of the frame (Eq. RRFVel).  window_beta: window
+ * speed in units of c; < 0 selects the mean beam velocity at t' = 0. */
+typedef struct {
+    double gamma_boost, window_beta;
+} pic_frame;
+
+/* Electron beam defined in the lab at lab time 0 (section 3: "after definition
+ * in the LRF the code calculates the equivalence to the RRF").  Gaussian with rms
+ * sizes sigma_cells[0..1] (transverse, frame invariant, cells) and sigma_cells[2]
+ * (longitudinal, boosted-frame cells; the lab rms length follows from Eq. Belon),
+ * lab Lorentz factor gamma_lab with relative rms spread, normalised rms emittances
+ * emit_n_m (m).  normals: HOST pointer to 6 x n_macro standard-normal draws in
+ * rows (x, y, z, ux, uy, energy); read during pic_init only.  The beam centre sits
+ * on the box axis, z_center_cells from the window's back face at t' = 0. */
+typedef struct {
+    int64_t n_macro;
+    double charge_C, gamma_lab, rel_energy_spread_rms;
+    double sigma_cells[3], emit_n_m[2], z_center_cells;
+    const double *normals;
+} pic_beam;
+
+/* Cold plasma at rest in the lab with lab density n0 (cm^-3) on a regular
+ * lattice of ppc[0] x ppc[1] x ppc[2] particles per cell; boosted density
+ * gamma_R n0 (Eq. Nnormi).  Longitudinal lab profile: zero before z_start,
+ * linear up-ramp over ramp_up, flat to z_start + length, zero after;
+ * length <= 0 means uniform everywhere.  Lab positions are measured from the
+ * beam centre at lab time 0.  ions = 1 adds immobile lab ions on the same
+ * lattice (their current j_i = v_R rho_i is computed directly, section 1). */
+typedef struct {
+    double n0_lab_cm3;
+    int32_t ppc[3], ions;
+    double z_start_lab_m, length_lab_m, ramp_up_lab_m;
+} pic_plasma;
+
+/* Ideal undulator in the lab: B = B0 env (cos phi, sin phi, 0) (helical) or
+ * (0, sin phi, 0) (planar), phi = 2 pi (z - z_start) / period, B0 from the
+ * deflection parameter K; linear entrance and exit ramps of
+ * entrance_ramp_periods periods.  Transformed to the boosted frame with
+ * Eq. M1-M4 and applied analytically at the particles. */
+typedef struct {
+    int32_t kind, reserved;
+    double K, period_lab_m, z_start_lab_m, length_lab_m, entrance_ramp_periods;
+} pic_undulator;
+
+/* precision: PIC_FP64_PLAIN (absolute FP64 positions, FP64 fields, FP64 atomics)
+ *            or PIC_FP32_SPLIT (int32 cell + FP32 offset, FP32 fields, 64-bit
+ *            fixed-point current, particles binned by cell tile).
+ * pusher: PIC_BORIS, PIC_VAY or PIC_PUSHER_AUTO (Vay when an undulator is on).
+ * fp64_gamma_threshold: FP32 mode pushes particles above this Lorentz factor in FP64.
+ * fixed_point_frac_bits: 0 = automatic from the peak current bound.
+ * check_every: FP32 mode re-lays out its bins when needed, checked every this
+ *              many steps (a host synchronisation); 0 = 64.
+ * tile: cell tile of the FP32 binned kernels (each edge >= 4 and divides the grid,
+ *       LDS of one workgroup <= 64 KiB); 0 = 8x8x4.
+ * max_steps: sizing of the plasma capacity of the FP64 mode (injection between
+ *            compactions, or over the whole run when record = 1).
+ * record: 1 keeps particle slots stable (no compaction) so that
+ *         pic_adjoint_step() can follow them; FP64 mode only.
+ * variant: launch shape of the FP32 particle kernel: 0 = 512 threads per
+ *          workgroup with 2 waves per SIMD, 1 = 384 threads with 3 waves per SIMD.
+ * stream: hipStream_t for all launches (NULL: null stream). */
+typedef struct {
+    int32_t precision, pusher;
+    double fp64_gamma_threshold;
+    int32_t fixed_point_frac_bits, check_every;
+    int32_t tile[3], max_steps;
+    int32_t record, variant;
+    void *stream;
+} pic_options;
+
+typedef struct {
+    uint64_t arena_bytes;    /* device bytes the caller must provide */
+    uint64_t state_bytes;    /* device bytes of one pic_get_state() snapshot */
+    int64_t beam_capacity;   /* particle slots */
+    int64_t plasma_capacity;
+} pic_layout;
+
+/* Sizes of the caller-owned buffers for this configuration.  Host only, no GPU. */
+PIC_API pic_status pic_query_layout(const pic_grid *g, const pic_frame *f, const pic_beam *b, const pic_plasma *p,
+                            const pic_undulator *u, const pic_options *o, pic_layout *out);
+
+/* Derived normalised constants (host only, no GPU): for checking the host logic. */
+typedef struct {
+    double dt, gamma_R, beta_R, u_R, n_ref_m3, w_beam, n0_norm, k_u_lab, B0_norm, k_bunch;
+    double elongation, sigma_z_lab_cells, z_offset_cells;
+    int32_t frac_bits, pusher;
+} pic_derived;
+PIC_API pic_status pic_derive(const pic_grid *g, const pic_frame *f, const pic_beam *b, const pic_plasma *p,
+                      const pic_undulator *u, const pic_options *o, pic_derived *out);
+
+/* Create a context on the current HIP device, borrowing arena (device memory of
+ * at least layout.arena_bytes).  Samples and transforms the beam (FP64, on the
+ * device), loads the plasma lattice, zeroes the fields.  *out is NULL on error. */
+PIC_API pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, const pic_plasma *p,
+                    const pic_undulator *u, const pic_options *o, void *arena, uint64_t arena_bytes,
+                    pic_ctx **out);
+
+/* Advance nsteps steps (gather, push, deposit, ion current, FDTD, window,
+ * injection).  Asynchronous on the context stream. */
+PIC_API pic_status pic_step(pic_ctx *c, int32_t nsteps);
+
+/* Diagnostics (synchronising).  mask: PIC_DIAG_MOMENTS | PIC_DIAG_BUNCHING |
+ * PIC_DIAG_ENERGY | PIC_DIAG_GAUSS.  Bunching b(k) = |sum_beam w exp(i k z')| /
+ * sum w at k = 2 pi / bunch_period_cells and 2k (boosted frame, fixed t').
+ * Gauss: r = div E - rho on nodes at least 8 planes from the z faces; reports
+ * max |r| and max |r - r_prev| against the previous Gauss call (planes aligned
+ * by the window shift).  All sums in FP64. */
+enum { PIC_DIAG_MOMENTS = 1, PIC_DIAG_BUNCHING = 2, PIC_DIAG_ENERGY = 4, PIC_DIAG_GAUSS = 8 };
+typedef struct {
+    double t, step, k0, n_beam, n_plasma, beam_lost, wsum;
+    double mean[3], sigma[3], umean[3], usigma[3], emit[2]; /* cells; emit in cells (x D for metres) */
+    double b1_re, b1_im, b1_abs, b2_re, b2_im, b2_abs;
+    double field_energy, kin_beam, kin_plasma;
+    double gauss_max, gauss_drift, rho_max;
+    double window_beta, frac_bits, error_flags;
+} pic_diag_out;
+PIC_API pic_status pic_diag(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_diag_out *out);
+
+/* Named arrays in canonical order (fields: logical window planes, x fastest;
+ * particles: FP64 mode in slot order, FP32 mode in bin order; FP32 positions
+ * are returned as absolute FP64 coordinates).  dst: DEVICE buffer.  count
+ * receives the element count (dst may be NULL to query).  Synchronising. */
+enum {
+    PIC_A_EX = 0, PIC_A_EY, PIC_A_EZ, PIC_A_BX, PIC_A_BY, PIC_A_BZ, /* double */
+    PIC_A_BEAM = 16,   /* double [7][n]: x y z ux uy uz w  (n = slots) */
+    PIC_A_BEAM_ALIVE,  /* int32 [n] */
+    PIC_A_PLASMA,      /* double [7][n] */
+    PIC_A_PLASMA_ALIVE /* int32 [n] */
+};
+PIC_API pic_status pic_read(pic_ctx *c, int32_t which, void *dst, int64_t *count);
+
+/* Overwrite named arrays (same layouts as pic_read, src on the DEVICE):
+ * fields, and particle phase space of existing slots (FP64 mode). */
+PIC_API pic_status pic_write(pic_ctx *c, int32_t which, const void *src, int64_t count);
+
+/* Checkpoint: copy the full dynamic state (particles, fields, window origin,
+ * step counter, injection cursors) into / out of a DEVICE buffer of
+ * layout.state_bytes.  Used for resume and by the adjoint's recomputation. */
+PIC_API pic_status pic_get_state(pic_ctx *c, void *dst);
+PIC_API pic_status pic_set_state(pic_ctx *c, const void *src);
+
+/* Adjoint (FP64 mode with record = 1).  The adjoint vector has the layout of
+ * the forward state: [beam x,y,z,ux,uy,uz (beam slots each)] [plasma 6 x plasma
+ * slots] [E 3 x cells] [B 3 x cells], doubles on the DEVICE, particle blocks
+ * sized by pic_lambda_len().  pic_adjoint_seed_bunching() writes dL/dstate of
+ * L = |b(2 pi / bunch_period)| for the current state and returns L.
+ * pic_adjoint_step(): precondition -- the context holds forward state n (e.g.
+ * restored with pic_set_state); lam holds the adjoint of state n+1 and is
+ * overwritten with the adjoint of state n (slots injected during step n are
+ * dropped); grad[0] += K dL/dK and grad[1] += n0 dL/dn0 contributions of the
+ * step (host doubles).  The forward state is left unchanged. */
+PIC_API int64_t pic_lambda_len(const pic_ctx *c);
+PIC_API pic_status pic_adjoint_seed_bunching(pic_ctx *c, double bunch_period_cells, void *lam, double *loss);
+PIC_API pic_status pic_adjoint_step(pic_ctx *c, void *lam, double grad[2]);
+
+/* Kernel timing with HIP events recorded on the context stream around each
+ * launch class: [0] fused particle kernels (gather, push, deposit), [1] FDTD
+ * (both B half steps, E update, Mur faces), [2] window, ion current,
+ * injection and binning, [3] whole steps.  pic_timing(c, 1) clears and starts
+ * collecting, pic_timing(c, 0) stops.  pic_timing_read() synchronises and
+ * returns the summed milliseconds and the number of timed launches per class. */
+PIC_API pic_status pic_timing(pic_ctx *c, int32_t enable);
+PIC_API pic_status pic_timing_read(pic_ctx *c, double ms[4], int64_t launches[4]);
+
+PIC_API pic_status pic_sync(pic_ctx *c);
+PIC_API void pic_free(pic_ctx *c);
+PIC_API const char *pic_last_error(const pic_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

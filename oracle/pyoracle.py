@@ -182,24 +182,27 @@ class Sim:
         return self.cfg.nx * self.cfg.ny * self.cfg.nz
 
     def _view(self, ptr, n, dtype):
+        """Writable view of n elements at ptr; valid only while this simulation lives."""
         if n == 0:
             return np.zeros(0, dtype)
         buf = (C.c_char * (n * np.dtype(dtype).itemsize)).from_address(ptr)
         return np.frombuffer(buf, dtype=dtype, count=n)
 
     def field(self, name) -> np.ndarray:
-        """View (nz, ny, nx) of a field in logical window order."""
+        """Writable view (nz, ny, nx) of a field in logical window order (valid while the simulation lives)."""
         k = FIELD_NAMES.index(name) if isinstance(name, str) else int(name)
         v = self._view(self.L.orc_field(self.h, k), self.nc, self.dtype)
         return v.reshape(self.cfg.nz, self.cfg.ny, self.cfg.nx)
 
-    def particles(self, species: int) -> dict:
+    def particles(self, species: int, view: bool = False) -> dict:
+        """Particle arrays of a species (0 beam, 1 plasma): copies, or writable
+        views valid while the simulation lives when ``view`` is set."""
         n = self.info().n_beam if species == 0 else self.info().n_plasma
         out = {}
         for k, name in enumerate(("x", "y", "z", "ux", "uy", "uz", "w")):
             out[name] = self._view(self.L.orc_particles(self.h, species, k), n, self.dtype)
         out["alive"] = self._view(self.L.orc_alive(self.h, species), n, np.int32)
-        return out
+        return out if view else {k: v.copy() for k, v in out.items()}
 
     def rho(self, mask: int = 7) -> np.ndarray:
         r = np.zeros(self.nc, self.dtype)

@@ -1,0 +1,169 @@
+"""ctypes mirror of include/pic.h -- argument marshalling only.
+
+Every function here forwards to the HIP library libpicrrf.so with the same
+name; no simulation arithmetic happens in Python.  Loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpicrrf.so")
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ERANGE = 0, -1, -2, -3, -4, -5
+PIC_FP64_PLAIN, PIC_FP32_SPLIT = 0, 1
+PIC_BORIS, PIC_VAY, PIC_PUSHER_AUTO = 0, 1, -1
+PIC_DIAG_MOMENTS, PIC_DIAG_BUNCHING, PIC_DIAG_ENERGY, PIC_DIAG_GAUSS = 1, 2, 4, 8
+PIC_A_EX, PIC_A_EY, PIC_A_EZ, PIC_A_BX, PIC_A_BY, PIC_A_BZ = range(6)
+PIC_A_BEAM, PIC_A_BEAM_ALIVE, PIC_A_PLASMA, PIC_A_PLASMA_ALIVE = 16, 17, 18, 19
+
+STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVICE", -4: "PIC_ESTATE", -5: "PIC_ERANGE"}
+
+
+class pic_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved", C.c_int32),
+                ("dx_m", C.c_double), ("cfl", C.c_double)]
+
+
+class pic_frame(C.Structure):
+    _fields_ = [("gamma_boost", C.c_double), ("window_beta", C.c_double)]
+
+
+class pic_beam(C.Structure):
+    _fields_ = [("n_macro", C.c_int64), ("charge_C", C.c_double), ("gamma_lab", C.c_double),
+                ("rel_energy_spread_rms", C.c_double), ("sigma_cells", C.c_double * 3),
+                ("emit_n_m", C.c_double * 2), ("z_center_cells", C.c_double), ("normals", C.c_void_p)]
+
+
+class pic_plasma(C.Structure):
+    _fields_ = [("n0_lab_cm3", C.c_double), ("ppc", C.c_int32 * 3), ("ions", C.c_int32),
+                ("z_start_lab_m", C.c_double), ("length_lab_m", C.c_double), ("ramp_up_lab_m", C.c_double)]
+
+
+class pic_undulator(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("K", C.c_double), ("period_lab_m", C.c_double),
+                ("z_start_lab_m", C.c_double), ("length_lab_m", C.c_double), ("entrance_ramp_periods", C.c_double)]
+
+
+class pic_options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("pusher", C.c_int32), ("fp64_gamma_threshold", C.c_double),
+                ("fixed_point_frac_bits", C.c_int32), ("check_every", C.c_int32), ("tile", C.c_int32 * 3),
+                ("max_steps", C.c_int32), ("record", C.c_int32), ("variant", C.c_int32), ("stream", C.c_void_p)]
+
+
+class pic_layout(C.Structure):
+    _fields_ = [("arena_bytes", C.c_uint64), ("state_bytes", C.c_uint64), ("beam_capacity", C.c_int64),
+                ("plasma_capacity", C.c_int64)]
+
+
+class pic_derived(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("dt", "gamma_R", "beta_R", "u_R", "n_ref_m3", "w_beam", "n0_norm",
+                                          "k_u_lab", "B0_norm", "k_bunch", "elongation", "sigma_z_lab_cells",
+                                          "z_offset_cells")] + [("frac_bits", C.c_int32), ("pusher", C.c_int32)]
+
+
+class pic_diag_out(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("t", "step", "k0", "n_beam", "n_plasma", "beam_lost", "wsum")] + \
+               [("mean", C.c_double * 3), ("sigma", C.c_double * 3), ("umean", C.c_double * 3),
+                ("usigma", C.c_double * 3), ("emit", C.c_double * 2)] + \
+               [(n, C.c_double) for n in ("b1_re", "b1_im", "b1_abs", "b2_re", "b2_im", "b2_abs", "field_energy",
+                                          "kin_beam", "kin_plasma", "gauss_max", "gauss_drift", "rho_max",
+                                          "window_beta", "frac_bits", "error_flags")]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else float(v)
+        return out
+
+
+EXPORTS = ("pic_query_layout", "pic_derive", "pic_init", "pic_step", "pic_diag", "pic_read", "pic_write",
+           "pic_get_state", "pic_set_state", "pic_lambda_len", "pic_adjoint_seed_bunching", "pic_adjoint_step",
+           "pic_timing", "pic_timing_read", "pic_sync", "pic_free", "pic_last_error")
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libpicrrf.so (built in-tree by paper_2411_04703_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    cfg = [P(pic_grid), P(pic_frame), P(pic_beam), P(pic_plasma), P(pic_undulator), P(pic_options)]
+    L.pic_query_layout.argtypes = cfg + [P(pic_layout)]
+    L.pic_derive.argtypes = cfg + [P(pic_derived)]
+    L.pic_init.argtypes = cfg + [C.c_void_p, C.c_uint64, P(C.c_void_p)]
+    L.pic_step.argtypes = [C.c_void_p, C.c_int32]
+    L.pic_diag.argtypes = [C.c_void_p, C.c_uint32, C.c_double, P(pic_diag_out)]
+    L.pic_read.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, P(C.c_int64)]
+    L.pic_write.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]
+    L.pic_get_state.argtypes = [C.c_void_p, C.c_void_p]
+    L.pic_set_state.argtypes = [C.c_void_p, C.c_void_p]
+    L.pic_lambda_len.argtypes = [C.c_void_p]
+    L.pic_lambda_len.restype = C.c_int64
+    L.pic_adjoint_seed_bunching.argtypes = [C.c_void_p, C.c_double, C.c_void_p, P(C.c_double)]
+    L.pic_adjoint_step.argtypes = [C.c_void_p, C.c_void_p, P(C.c_double)]
+    L.pic_timing.argtypes = [C.c_void_p, C.c_int32]
+    L.pic_timing_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
+    L.pic_sync.argtypes = [C.c_void_p]
+    L.pic_free.argtypes = [C.c_void_p]
+    L.pic_last_error.argtypes = [C.c_void_p]
+    L.pic_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("pic_lambda_len", "pic_last_error", "pic_free"):
+            getattr(L, name).restype = C.c_int
+    L.pic_free.restype = None
+    _lib = L
+    return L
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHER_AUTO, record=0, max_steps=0,
+                          check_every=0, tile=(0, 0, 0), frac_bits=0, gamma_threshold=0.0, stream=None,
+                          normals=None, variant=0):
+    """Fill the C structs from a workload dictionary (plain field copies)."""
+    g, fr, b, p, u = w["grid"], w["frame"], w["beam"], w["plasma"], w["undulator"]
+    grid = pic_grid(g["nx"], g["ny"], g["nz"], 0, g["dx_m"], g["cfl"])
+    frame = pic_frame(fr["gamma_boost"], fr["window_beta"])
+    beam = pic_beam()
+    beam.n_macro = b["n_macro"]
+    beam.charge_C = b["charge_C"]
+    beam.gamma_lab = b["gamma_lab"]
+    beam.rel_energy_spread_rms = b["rel_energy_spread_rms"]
+    beam.sigma_cells[:] = b["sigma_cells"]
+    beam.emit_n_m[:] = b["emit_n_m"]
+    beam.z_center_cells = b["z_center_cells"]
+    beam.normals = None if normals is None else normals.ctypes.data
+    plasma = pic_plasma()
+    plasma.n0_lab_cm3 = p["n0_lab_cm3"]
+    plasma.ppc[:] = p["ppc"]
+    plasma.ions = p["ions"]
+    plasma.z_start_lab_m, plasma.length_lab_m, plasma.ramp_up_lab_m = (p["z_start_lab_m"], p["length_lab_m"],
+                                                                       p["ramp_up_lab_m"])
+    und = pic_undulator(u["kind"], 0, u["K"], u["period_lab_m"], u["z_start_lab_m"], u["length_lab_m"],
+                        u["entrance_ramp_periods"])
+    opt = pic_options()
+    opt.precision = precision
+    opt.pusher = pusher
+    opt.fp64_gamma_threshold = gamma_threshold
+    opt.fixed_point_frac_bits = frac_bits
+    opt.check_every = check_every
+    opt.tile[:] = list(tile)
+    opt.max_steps = max_steps
+    opt.record = record
+    opt.variant = variant
+    opt.stream = stream
+    return grid, frame, beam, plasma, und, opt

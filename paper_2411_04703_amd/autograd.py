@@ -1,0 +1,76 @@
+"""Gradient of the final bunching factor w.r.t. undulator K and plasma density.
+
+``bunching_loss(K, n0, ...)`` is a ``torch.autograd.Function``: the forward
+pass runs the FP64 path in record mode and keeps a full-state checkpoint
+every ``every`` steps; the backward pass walks the segments in reverse,
+restores each checkpoint, recomputes and keeps the segment's states, then
+applies the hand-written adjoint step (``pic_adjoint_step``) once per step.
+The library returns K dL/dK and n0 dL/dn0 (both parameters enter linearly:
+the external field is proportional to K, every plasma weight to n0).
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+import torch
+
+from . import abi
+from .sim import Sim
+
+
+class BunchingLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, K, n0, w, normals, nsteps, every, bunch_period):
+        w2 = copy.deepcopy(w)
+        w2["undulator"]["K"] = float(K)
+        w2["plasma"]["n0_lab_cm3"] = float(n0)
+        sim = Sim(w2, normals, precision=abi.PIC_FP64_PLAIN, record=1, max_steps=int(nsteps) + 2)
+        ckpts = []
+        for n in range(int(nsteps)):
+            if n % every == 0:
+                ckpts.append(sim.get_state())
+            sim.step(1)
+        lam = torch.zeros(sim.lambda_len(), dtype=torch.float64, device=sim.device)
+        L = sim.adjoint_seed(lam, bunch_period)
+        ctx.sim, ctx.ckpts, ctx.lam = sim, ckpts, lam
+        ctx.nsteps, ctx.every = int(nsteps), int(every)
+        ctx.K, ctx.n0 = float(K), float(n0)
+        return torch.tensor(L, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gL):
+        sim, lam = ctx.sim, ctx.lam
+        grad = np.zeros(2)
+        buf = [sim.new_state_buffer() for _ in range(ctx.every)]
+        for seg in reversed(range(len(ctx.ckpts))):
+            a = seg * ctx.every
+            b = min(a + ctx.every, ctx.nsteps)
+            sim.set_state(ctx.ckpts[seg])
+            for n in range(a, b):  # recompute the segment's states
+                sim.get_state(buf[n - a])
+                if n + 1 < b:
+                    sim.step(1)
+            for n in reversed(range(a, b)):
+                sim.set_state(buf[n - a])
+                sim.adjoint_step(lam, grad)
+        g = float(gL)
+        dK = grad[0] / ctx.K * g if ctx.K != 0 else 0.0
+        dn = grad[1] / ctx.n0 * g if ctx.n0 != 0 else 0.0
+        ctx.log_grads = grad.copy()
+        return (torch.tensor(dK, dtype=torch.float64), torch.tensor(dn, dtype=torch.float64),
+                None, None, None, None, None)
+
+
+def bunching_loss(K, n0, w, normals, nsteps, every=50, bunch_period=20.0):
+    """L = |b(2 pi / bunch_period)| after nsteps; differentiable in K and n0 (torch scalars)."""
+    return BunchingLoss.apply(K, n0, w, normals, nsteps, every, bunch_period)
+
+
+def bunching_grad(w, normals, nsteps, every=50, bunch_period=20.0):
+    """(L, K dL/dK, n0 dL/dn0) for the workload's own K and n0."""
+    K = torch.tensor(w["undulator"]["K"], dtype=torch.float64, requires_grad=True)
+    n0 = torch.tensor(w["plasma"]["n0_lab_cm3"], dtype=torch.float64, requires_grad=True)
+    L = bunching_loss(K, n0, w, normals, nsteps, every, bunch_period)
+    L.backward()
+    return float(L), float(K.grad) * float(K), float(n0.grad) * float(n0)

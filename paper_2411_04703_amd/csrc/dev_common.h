@@ -1,0 +1,207 @@
+// dev_common.h -- device-side building blocks shared by the HIP kernels:
+// run parameters, ring-buffer indexing of the moving window, quadratic
+// B-spline weights, the boosted-frame undulator field and the pushers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// Normalised run constants (length = cell edge D, time = D / c).
+struct Params {
+    int nx, ny, nz, plane;      // plane = nx * ny
+    int64_t nc;                 // cells
+    double dt, gR, bR, uR;      // time step, frame gamma, beta, gamma*beta
+    double zoff;                // z_lab = gR (z - zoff + bR t)
+    // undulator (lab cells)
+    int und_kind, pusher;
+    double ku, z0u, Lu, Ru, B0;
+    // plasma (lab cells)
+    int has_plasma, ions, ppx, ppy, ppz, pad0;
+    double n0n, z0p, Lp, Rp, wsheet; // wsheet = gR n0n / (ppx ppy ppz)
+    double wbeam;
+    double gthr;                // FP32 mode: FP64 push above this gamma
+    int frac_bits, pad1;
+    double fscale, finv;        // 2^frac_bits and its inverse
+    int tx, ty, tz, ntx, nty, ntz, nbins, pad2;
+};
+
+// Window position during one step (host-decided, deterministic from the step count).
+struct StepCtx {
+    int64_t step;
+    double t, t1;       // t' at the start and end of the step
+    int64_t k0;         // absolute plane of logical plane 0 during the step
+    int64_t k0n;        // after the end-of-step shift
+    int k0r, k0nr;      // ring offsets: k0 mod nz, k0n mod nz
+    int shift, pad;
+};
+
+__host__ __device__ inline int wrapi(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Ring plane of logical window plane l (0 <= l < nz).
+__host__ __device__ inline int ring_plane(int l, int k0r, int nz) {
+    int p = l + k0r;
+    return p >= nz ? p - nz : p;
+}
+
+__host__ __device__ inline int64_t cell_index(const Params &P, int i, int j, int p) {
+    return (int64_t)wrapi(i, P.nx) + (int64_t)P.nx * ((int64_t)wrapi(j, P.ny) + (int64_t)P.ny * p);
+}
+
+// Quadratic B-spline S(d) = 3/4 - d^2 (|d| <= 1/2), (3/2 - |d|)^2 / 2 (1/2 < |d| < 3/2).
+template <typename T> __device__ inline T spline2(T d) {
+    T a = d < T(0) ? -d : d;
+    if (a <= T(0.5)) return T(0.75) - d * d;
+    if (a < T(1.5)) {
+        T t = T(1.5) - a;
+        return T(0.5) * t * t;
+    }
+    return T(0);
+}
+
+template <typename T> __device__ inline T dspline2(T d) {
+    T a = d < T(0) ? -d : d;
+    if (a <= T(0.5)) return T(-2) * d;
+    if (a < T(1.5)) return d >= T(0) ? -(T(1.5) - d) : (T(1.5) + d);
+    return T(0);
+}
+
+// Three weights of the nearest node n and its neighbours for offset d = x - n, |d| <= 1/2.
+template <typename T> __device__ inline void weights3(T d, T w[3]) {
+    T a = T(0.5) - d, b = T(0.5) + d;
+    w[0] = T(0.5) * a * a;
+    w[1] = T(0.75) - d * d;
+    w[2] = T(0.5) * b * b;
+}
+
+// ---------------------------------------------------------------- external field
+// Lab field B = B0 env (cos phi, sin phi, 0) (helical) / (0, sin phi, 0) (planar),
+// phi = k_u a with a = z_lab - z_start; boosted: B' = gR B_perp, E' = gR bR (zhat x B).
+__device__ inline void und_env(const Params &P, double a, double &env, double &denv) {
+    env = 0.0;
+    denv = 0.0;
+    if (a < 0.0 || a > P.Lu) return;
+    if (P.Ru <= 0.0) {
+        env = 1.0;
+        return;
+    }
+    double up = a / P.Ru, dn = (P.Lu - a) / P.Ru;
+    if (up < 1.0 && up <= dn) {
+        env = up;
+        denv = 1.0 / P.Ru;
+    } else if (dn < 1.0) {
+        env = dn;
+        denv = -1.0 / P.Ru;
+    } else
+        env = 1.0;
+}
+
+// Field at boosted (z, t) plus its z derivative (FP64).
+__device__ inline void ext_field64(const Params &P, double z, double t, double E[3], double B[3], double dE[3],
+                                   double dB[3]) {
+    E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0;
+    dE[0] = dE[1] = dE[2] = dB[0] = dB[1] = dB[2] = 0.0;
+    if (P.und_kind == 0) return;
+    double a = P.gR * (z - P.zoff + P.bR * t) - P.z0u;
+    double env, denv;
+    und_env(P, a, env, denv);
+    if (env == 0.0 && denv == 0.0) return;
+    double sn, cs;
+    sincos(P.ku * a, &sn, &cs);
+    double bx, by, dbx, dby;
+    if (P.und_kind == 1) {
+        bx = P.B0 * env * cs;
+        by = P.B0 * env * sn;
+        dbx = P.B0 * (denv * cs - env * P.ku * sn);
+        dby = P.B0 * (denv * sn + env * P.ku * cs);
+    } else {
+        bx = 0.0;
+        dbx = 0.0;
+        by = P.B0 * env * sn;
+        dby = P.B0 * (denv * sn + env * P.ku * cs);
+    }
+    double ge = P.gR * P.bR;
+    E[0] = -ge * by;
+    E[1] = ge * bx;
+    B[0] = P.gR * bx;
+    B[1] = P.gR * by;
+    dE[0] = -ge * P.gR * dby;
+    dE[1] = ge * P.gR * dbx;
+    dB[0] = P.gR * P.gR * dbx;
+    dB[1] = P.gR * P.gR * dby;
+}
+
+// ---------------------------------------------------------------- pushers (q/m = -1)
+template <typename T> __device__ inline T dot3(const T a[3], const T b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+template <typename T> __device__ inline void cross3(const T a[3], const T b[3], T o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Boris: half kick, rotation, half kick.
+template <typename T> __device__ inline void push_boris(T dt, const T u[3], const T E[3], const T B[3], T out[3]) {
+    T a = T(-0.5) * dt;
+    T um[3], Tv[3], S[3], up[3], c[3];
+    for (int d = 0; d < 3; ++d) um[d] = u[d] + a * E[d];
+    T gm = sqrt(T(1) + dot3(um, um));
+    for (int d = 0; d < 3; ++d) Tv[d] = a * B[d] / gm;
+    T tt = dot3(Tv, Tv);
+    for (int d = 0; d < 3; ++d) S[d] = T(2) * Tv[d] / (T(1) + tt);
+    cross3(um, Tv, c);
+    for (int d = 0; d < 3; ++d) up[d] = um[d] + c[d];
+    cross3(up, S, c);
+    for (int d = 0; d < 3; ++d) out[d] = um[d] + c[d] + a * E[d];
+}
+
+// Vay: velocity average in the magnetic term, closed-form Lorentz factor.
+template <typename T> __device__ inline void push_vay(T dt, const T u[3], const T E[3], const T B[3], T out[3]) {
+    T a = T(-0.5) * dt;
+    T g0 = sqrt(T(1) + dot3(u, u));
+    T v0[3], c[3], u1[3], tau[3], t[3];
+    for (int d = 0; d < 3; ++d) v0[d] = u[d] / g0;
+    cross3(v0, B, c);
+    for (int d = 0; d < 3; ++d) u1[d] = u[d] + T(2) * a * E[d] + a * c[d];
+    for (int d = 0; d < 3; ++d) tau[d] = a * B[d];
+    T us = dot3(u1, tau), tau2 = dot3(tau, tau);
+    T sig = T(1) + dot3(u1, u1) - tau2;
+    T D = sqrt(sig * sig + T(4) * (tau2 + us * us));
+    T gn = sqrt(T(0.5) * (sig + D));
+    for (int d = 0; d < 3; ++d) t[d] = tau[d] / gn;
+    T sf = T(1) / (T(1) + dot3(t, t));
+    T ut = dot3(u1, t);
+    cross3(u1, t, c);
+    for (int d = 0; d < 3; ++d) out[d] = sf * (u1[d] + ut * t[d] + c[d]);
+}
+
+template <typename T> __device__ inline void push(int pusher, T dt, const T u[3], const T E[3], const T B[3], T out[3]) {
+    if (pusher == 1)
+        push_vay(dt, u, E, B, out);
+    else
+        push_boris(dt, u, E, B, out);
+}
+
+// plasma lab profile in [0, 1] (linear up-ramp, flat, zero outside; Lp <= 0: uniform)
+__host__ __device__ inline double plasma_profile(double Lp, double z0p, double Rp, double zl) {
+    if (Lp <= 0.0) return 1.0;
+    double a = zl - z0p;
+    if (a < 0.0 || a >= Lp) return 0.0;
+    if (Rp > 0.0 && a < Rp) return a / Rp;
+    return 1.0;
+}
+
+// boosted position of lattice sheet l at time t: ((l + 1/2) / ppz) - bR t
+__host__ __device__ inline double sheet_z(int64_t l, int ppz, double bR, double t) {
+    return ((double)l + 0.5) / ppz - bR * t;
+}
+
+// per-particle weight of sheet l (boosted density gR n(z_lab), Eq. Nnormi)
+__host__ __device__ inline double sheet_weight(const Params &P, int64_t l) {
+    double zl = P.gR * (sheet_z(l, P.ppz, P.bR, 0.0) - P.zoff);
+    return P.wsheet * plasma_profile(P.Lp, P.z0p, P.Rp, zl);
+}
+
+}  // namespace pic

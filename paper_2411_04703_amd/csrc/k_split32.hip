@@ -1,0 +1,1324 @@
+// k_split32.hip -- FP32 split-precision path.
+//
+// Particles: int32 logical cell index (i + nx (j + ny l), l = window plane)
+// plus FP32 offsets in [0, 1), FP32 momenta and weight: 32 bytes each, SoA.
+// They are kept binned by cell tile ("bins") in two buffers; every step reads
+// the current buffer and appends each surviving particle to its destination
+// bin in the other buffer (wave-aggregated slot reservation), so the bins are
+// exact after every step without a separate sort.  A full bin sends its
+// particles to an overflow tail, processed the next step by the untiled path;
+// the bins are re-laid out from the counts when the periodic host check finds
+// overflow or a bin close to its capacity.
+//
+// Work: one (bin, chunk) item at a time per workgroup, items taken from an
+// atomic counter by a persistent grid.  Per item: stage the tile's E, B (+
+// halo) in LDS, gather with quadratic shapes, push (FP32; FP64 above a
+// Lorentz-factor threshold), move, and deposit Esirkepov currents as 64-bit
+// fixed-point integers into an LDS tile that is flushed with global 64-bit
+// integer atomics.  Integer sums do not depend on their order: the current,
+// and all that follows from it, is bitwise reproducible.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int ST = 512;    // threads per workgroup
+constexpr int CH = 4096;   // particles per work item
+constexpr int WT = 512;    // threads of the work-list kernels
+
+struct Store {
+    Part32 buf[2];
+    int64_t *off[2];       // nbins + 1 slot offsets of each buffer
+    int32_t *cnt[2];       // per-buffer bin counts (may exceed the capacity: the excess is in the overflow tail)
+    int32_t *ovf[2];       // per-buffer overflow counts
+    int64_t bin_slots;     // slots of the bin region
+    int64_t ovf_cap;
+    int64_t n_flat;        // init only
+};
+
+struct SpeciesIO;
+
+struct SplitState {
+    Store s[2];            // 0 beam, 1 plasma
+    int4 *items;
+    int32_t *nitems, *next;
+    int64_t items_cap;
+    int64_t *scan_part;
+    int32_t *tmpcnt;       // 2 x nbins
+    int64_t *tmpoff;       // 2 x (nbins + 2)
+    int grid;              // persistent grid of the step kernel
+    int tpb;               // its workgroup size (launch shape variant)
+    int lds_bytes;
+    SpeciesIO *ios;        // device descriptors: [cur 0][2], [cur 1][2], [flat init][2]
+};
+
+static SplitState &SS(Ctx &c) { return *static_cast<SplitState *>(c.split); }
+
+static int lds_bytes_of(const Params &P, int &ebytes) {
+    int nE = (P.tx + 3) * (P.ty + 3) * (P.tz + 3);
+    int nJ = (P.tx + 4) * (P.ty + 5) * (P.tz + 5) + (P.tx + 5) * (P.ty + 4) * (P.tz + 5) +
+             (P.tx + 5) * (P.ty + 5) * (P.tz + 4);
+    ebytes = (6 * nE * 4 + 15) & ~15;
+    return ebytes + 8 * nJ + 16 * (P.tz + 3);
+}
+
+// ---------------------------------------------------------------- helpers
+// Reserve one slot per active lane in bin `key` of cnt; lanes with equal keys
+// share one atomic.  Returns the rank within the bin (-1 for inactive lanes).
+// Called by every lane of the wave.
+__device__ inline int reserve_slot(bool active, int key, int32_t *cnt) {
+    int lane = __lane_id();
+    bool pending = active;
+    int slot = -1;
+    unsigned long long todo = __ballot(pending);
+    while (todo) {
+        int leader = __ffsll((unsigned long long)todo) - 1;
+        int lkey = __shfl(key, leader);
+        bool grp = pending && key == lkey;
+        unsigned long long gm = __ballot(grp);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[lkey], __popcll(gm));
+        base = __shfl(base, leader);
+        if (grp) {
+            slot = base + __popcll(gm & ((1ull << lane) - 1ull));
+            pending = false;
+        }
+        todo &= ~gm;
+    }
+    return slot;
+}
+
+struct OutStore {
+    Part32 buf;
+    const int64_t *off;
+    int32_t *cnt;
+    int32_t *ovf;
+    int64_t bin_slots, ovf_cap;
+};
+
+struct SpeciesIO {
+    Part32 in;
+    const int64_t *in_off;
+    const int32_t *in_cnt;
+    const int32_t *in_ovf;
+    int64_t in_ovf_start, in_ovf_cap;
+    OutStore out;
+};
+
+// append (active lanes) to bin `bin` of the output store; overflow tail when the bin is full
+__device__ inline void append(const OutStore &O, bool active, int bin, int cell, const float o[3], const float u[3],
+                              float w, int32_t *flags) {
+    int r = reserve_slot(active, active ? bin : 0, O.cnt);
+    if (!active) return;
+    int64_t b0 = O.off[bin], cap = O.off[bin + 1] - b0;
+    int64_t s;
+    if (r < cap) {
+        s = b0 + r;
+    } else {
+        int k = atomicAdd(O.ovf, 1);
+        if (k >= O.ovf_cap) {
+            atomicOr(flags, DFLAG_BIN_LOST);
+            return;
+        }
+        s = O.bin_slots + k;
+    }
+    Part32 b = O.buf;
+    b.cell[s] = cell;
+    b.ox[s] = o[0];
+    b.oy[s] = o[1];
+    b.oz[s] = o[2];
+    b.ux[s] = u[0];
+    b.uy[s] = u[1];
+    b.uz[s] = u[2];
+    b.w[s] = w;
+}
+
+__device__ inline int bin_of(const Params &P, int i, int j, int l) {
+    return i / P.tx + P.ntx * (j / P.ty + P.nty * (l / P.tz));
+}
+
+// number of valid particles of bin b in a store
+__device__ inline int bin_count(const int64_t *off, const int32_t *cnt, int b) {
+    int64_t cap = off[b + 1] - off[b];
+    int c = cnt[b];
+    return (int64_t)c < cap ? c : (int)cap;
+}
+
+// fixed-point value of one current contribution (round to nearest even)
+__device__ inline long long to_fixed(float v, double fscale, int32_t *flags) {
+    double s = (double)v * fscale;
+    if (!(fabs(s) <= 4.0e18)) {
+        atomicOr(flags, DFLAG_FIXED_OVERFLOW);
+        s = 0.0;
+    }
+    return (long long)rint(s);
+}
+
+// ---------------------------------------------------------------- particle math
+struct PState {
+    int i, j, l;
+    float o[3], u[3], w;
+};
+
+__device__ inline void load_particle(const Part32 &in, int64_t s, const Params &P, PState &q) {
+    int cell = in.cell[s];
+    q.i = cell % P.nx;
+    q.j = (cell / P.nx) % P.ny;
+    q.l = cell / P.plane;
+    q.o[0] = in.ox[s];
+    q.o[1] = in.oy[s];
+    q.o[2] = in.oz[s];
+    q.u[0] = in.ux[s];
+    q.u[1] = in.uy[s];
+    q.u[2] = in.uz[s];
+    q.w = in.w[s];
+}
+
+// undulator field at logical plane l: the plane's phase and envelope argument in
+// FP64, the in-cell phase advance k_u gR oz in FP32 by angle addition
+__device__ inline void ext_plane(const Params &P, int64_t k0, int l, double t, double &a_l, float &c, float &s) {
+    a_l = P.gR * ((double)(k0 + l) - P.zoff + P.bR * t) - P.z0u;
+    double sn, cs;
+    sincos(P.ku * a_l, &sn, &cs);
+    c = (float)cs;
+    s = (float)sn;
+}
+
+__device__ inline void ext32(const Params &P, double a_l, float cphi, float sphi, float oz, float E[3], float B[3]) {
+    double a = a_l + P.gR * (double)oz;
+    double env, denv;
+    und_env(P, a, env, denv);
+    if (env == 0.0) return;
+    float sd, cd;
+    sincosf((float)(P.ku * P.gR) * oz, &sd, &cd);
+    float c = cphi * cd - sphi * sd, s = sphi * cd + cphi * sd;
+    float b0 = (float)(P.B0 * env);
+    float bx = P.und_kind == 1 ? b0 * c : 0.0f, by = b0 * s;
+    float ge = (float)(P.gR * P.bR), g = (float)P.gR;
+    E[0] += -ge * by;
+    E[1] += ge * bx;
+    B[0] += g * bx;
+    B[1] += g * by;
+}
+
+// push in FP32, or FP64 above the Lorentz-factor threshold; false when non-finite
+__device__ inline bool push32(const Params &P, const float E[3], const float B[3], float u[3]) {
+    float g2 = 1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    float un[3];
+    if (g2 > (float)(P.gthr * P.gthr)) {
+        double ud[3] = {u[0], u[1], u[2]}, Ed[3] = {E[0], E[1], E[2]}, Bd[3] = {B[0], B[1], B[2]}, o[3];
+        push<double>(P.pusher, P.dt, ud, Ed, Bd, o);
+        for (int d = 0; d < 3; ++d) un[d] = (float)o[d];
+    } else {
+        push<float>(P.pusher, (float)P.dt, u, E, B, un);
+    }
+    for (int d = 0; d < 3; ++d) u[d] = un[d];
+    return isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]);
+}
+
+// Esirkepov weights of a move X0 -> X1 (coordinates relative to the particle's cell)
+struct Esk {
+    int base[3];
+    float S0[3][4], DS[3][4];
+};
+
+__device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
+    for (int d = 0; d < 3; ++d) {
+        int n0 = X0[d] >= 0.5f ? 1 : 0;
+        int n1 = (int)floorf(X1[d] + 0.5f);
+        e.base[d] = (n0 < n1 ? n0 : n1) - 1;
+        for (int m = 0; m < 4; ++m) {
+            float node = (float)(e.base[d] + m);
+            e.S0[d][m] = spline2<float>(X0[d] - node);
+            e.DS[d][m] = spline2<float>(X1[d] - node) - e.S0[d][m];
+        }
+    }
+}
+
+// every nonzero contribution: fn(c, r_along, r_a, r_b, value), r = node offsets
+// from the cell.  Per component c the Esirkepov current factorises:
+//   J_c(m, a, b) = f P_c[m] A_c[a][b],  P_c[m] = sum_{m' <= m} DS_c[m'],
+//   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3)
+// (a, b the other two axes in cyclic order).
+template <int C, typename F> __device__ inline void esk_component(const Esk &e, float f, F &&fn) {
+    constexpr int CA = C == 2 ? 0 : C + 1, CB = C == 0 ? 2 : C - 1;
+    float Pm[3];
+    Pm[0] = e.DS[C][0];
+    Pm[1] = Pm[0] + e.DS[C][1];
+    Pm[2] = Pm[1] + e.DS[C][2];
+    float ub[4], vb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        ub[b] = fmaf(0.5f, e.DS[CB][b], e.S0[CB][b]);
+        vb[b] = fmaf(1.0f / 3.0f, e.DS[CB][b], 0.5f * e.S0[CB][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            float A = fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
+            if (A == 0.0f) continue;
+            float fa = f * A;
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                if (Pm[m] != 0.0f) fn(C, e.base[C] + m, e.base[CA] + a, e.base[CB] + b, fa * Pm[m]);
+        }
+}
+
+template <typename F> __device__ inline void esk_visit(const Esk &e, float f, F &&fn) {
+    esk_component<0>(e, f, fn);
+    __builtin_amdgcn_sched_barrier(0);
+    esk_component<1>(e, f, fn);
+    __builtin_amdgcn_sched_barrier(0);
+    esk_component<2>(e, f, fn);
+}
+
+// carry new offsets into the cell, apply the window shift; false if the particle left the band
+__device__ inline bool renormalise(const Params &P, const StepCtx &S, PState &q) {
+    int dc[3];
+    for (int d = 0; d < 3; ++d) {
+        dc[d] = 0;
+        if (q.o[d] >= 1.0f) {
+            q.o[d] -= 1.0f;
+            dc[d] = 1;
+        } else if (q.o[d] < 0.0f) {
+            q.o[d] += 1.0f;
+            dc[d] = -1;
+            if (q.o[d] >= 1.0f) {  // a tiny negative offset rounded up to one cell
+                q.o[d] = 0.0f;
+                dc[d] = 0;
+            }
+        }
+    }
+    q.i += dc[0];
+    if (q.i < 0) q.i += P.nx;
+    if (q.i >= P.nx) q.i -= P.nx;
+    q.j += dc[1];
+    if (q.j < 0) q.j += P.ny;
+    if (q.j >= P.ny) q.j -= P.ny;
+    q.l += dc[2] - S.shift;
+    return q.l >= 3 && q.l < P.nz - 4;
+}
+
+// ---------------------------------------------------------------- shared per-particle arithmetic
+// This file is compiled without floating-point contraction: the tiled (LDS)
+// and the untiled (global) path run the very same operations in the same
+// order, so a particle's update does not depend on which path handled it --
+// which in turn depends on bin occupancy and atomic order.  FMAs are written
+// out explicitly where wanted.
+
+// field value accessors: staged LDS box (tiled) or ring-buffered global arrays (untiled)
+struct LdsBox {
+    const float *F;   // 6 boxes of nE floats
+    int nE, ex, ey;   // box index of (half-)node index k (relative to t0) is k + 1
+    __device__ float at(int comp, int x, int y, int z) const { return F[comp * nE + (x + 1) + ex * ((y + 1) + ey * (z + 1))]; }
+};
+struct GlobalField {
+    const Params *P;
+    const float *const *F;  // E0 E1 E2 B0 B1 B2
+    int i0, j0, l0, k0r;    // cell of the particle (indices relative to it)
+    __device__ float at(int comp, int x, int y, int z) const {
+        return F[comp][cell_index(*P, i0 + x, j0 + y, ring_plane(l0 + z, k0r, P->nz))];
+    }
+};
+
+// six Yee components with quadratic shapes; (x0, y0, z0) = cell relative to the accessor's origin
+template <class FA> __device__ inline void gather6(const FA &fa, const float o[3], int x0, int y0, int z0, float EB[6]) {
+    float wI[3][3], wH[3][3];
+    int bI[3], bH[3];
+    const int rel[3] = {x0, y0, z0};
+    for (int d = 0; d < 3; ++d) {
+        int nn = o[d] >= 0.5f ? 1 : 0;
+        weights3<float>(o[d] - (float)nn, wI[d]);
+        weights3<float>(o[d] - 0.5f, wH[d]);
+        bI[d] = rel[d] + nn - 1;  // first integer node
+        bH[d] = rel[d] - 1;       // first half node
+    }
+#pragma unroll
+    for (int comp = 0; comp < 6; ++comp) {
+        const int sx = comp == 0 || comp == 4 || comp == 5, sy = comp == 1 || comp == 3 || comp == 5,
+                  sz = comp == 2 || comp == 3 || comp == 4;
+        const float *wx = sx ? wH[0] : wI[0], *wy = sy ? wH[1] : wI[1], *wz = sz ? wH[2] : wI[2];
+        const int bx = sx ? bH[0] : bI[0], by = sy ? bH[1] : bI[1], bz = sz ? bH[2] : bI[2];
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                float r = fmaf(wx[2], fa.at(comp, bx + 2, by + b, bz + c),
+                               fmaf(wx[1], fa.at(comp, bx + 1, by + b, bz + c), wx[0] * fa.at(comp, bx, by + b, bz + c)));
+                acc = fmaf(wy[b] * wz[c], r, acc);
+            }
+        EB[comp] = acc;
+        __builtin_amdgcn_sched_barrier(0);  // keep the 27 loads of one component together (register pressure)
+    }
+}
+
+// external field, push, new (unwrapped) offsets X1; false when non-finite
+__device__ inline bool advance(const Params &P, float EB[6], bool ext, double a_l, float cphi, float sphi, PState &q,
+                               float X1[3]) {
+    float E[3] = {EB[0], EB[1], EB[2]}, B[3] = {EB[3], EB[4], EB[5]};
+    if (ext) ext32(P, a_l, cphi, sphi, q.o[2], E, B);
+    if (!push32(P, E, B, q.u)) return false;
+    float ig = 1.0f / sqrtf(1.0f + q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+    const float dt = (float)P.dt;
+    for (int d = 0; d < 3; ++d) X1[d] = q.o[d] + dt * (q.u[d] * ig);
+    return true;
+}
+
+// ---------------------------------------------------------------- untiled (global memory) update
+__device__ inline bool particle_global(const Params &P, const StepCtx &S, const float *const *F6, long long *Jx,
+                                       long long *Jy, long long *Jz, PState &q, int32_t *flags) {
+    if (!(q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f && q.o[2] >= 0.0f && q.o[2] < 1.0f &&
+          q.l >= 3 && q.l < P.nz - 4)) {
+        atomicOr(flags, DFLAG_NONFINITE);
+        return false;
+    }
+    GlobalField gf{&P, F6, q.i, q.j, q.l, S.k0r};
+    float EB[6];
+    gather6(gf, q.o, 0, 0, 0, EB);
+    double a_l = 0.0;
+    float cphi = 0.0f, sphi = 0.0f;
+    if (P.und_kind) ext_plane(P, S.k0, q.l, S.t, a_l, cphi, sphi);
+    float X1[3];
+    if (!advance(P, EB, P.und_kind != 0, a_l, cphi, sphi, q, X1)) {
+        atomicOr(flags, DFLAG_NONFINITE);
+        return false;
+    }
+    Esk e;
+    esk_setup(q.o, X1, e);
+    long long *J[3] = {Jx, Jy, Jz};
+    esk_visit(e, q.w / (float)P.dt, [&](int c, int ra, int rb, int rc, float v) {
+        int r[3];
+        r[c] = ra;
+        r[c == 2 ? 0 : c + 1] = rb;
+        r[c == 0 ? 2 : c - 1] = rc;
+        int p = ring_plane(q.l + r[2], S.k0r, P.nz);
+        long long iv = to_fixed(v, P.fscale, flags);
+        atomicAdd((unsigned long long *)&J[c][cell_index(P, q.i + r[0], q.j + r[1], p)], (unsigned long long)iv);
+    });
+    for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
+    return renormalise(P, S, q);
+}
+
+// ---------------------------------------------------------------- the step kernel
+// TPB threads per workgroup, at least MINW waves per SIMD (register budget 512 / MINW)
+template <int TPB, int MINW>
+__global__ void __launch_bounds__(TPB, MINW) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
+                                                          int32_t *next, const SpeciesIO *ios, FieldsT<float> f,
+                                                          long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int ex = P.tx + 3, ey = P.ty + 3, ez = P.tz + 3, nE = ex * ey * ez;
+    const int dJxx = P.tx + 4, dJxy = P.ty + 5, dJyx = P.tx + 5, dJyy = P.ty + 4, dJzx = P.tx + 5, dJzy = P.ty + 5;
+    const int nJx = dJxx * dJxy * (P.tz + 5), nJy = dJyx * dJyy * (P.tz + 5), nJz = dJzx * dJzy * (P.tz + 4);
+    const int nJ = nJx + nJy + nJz, nTab = P.tz + 3;
+    float *Fs = (float *)smem;
+    long long *Js = (long long *)(smem + ((6 * nE * 4 + 15) & ~15));
+    double *tabA = (double *)(Js + nJ);
+    float *tabC = (float *)(tabA + nTab), *tabS = tabC + nTab;
+    const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
+    const int total = *nitems;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(next, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int4 it = items[item];
+        const SpeciesIO &IO = ios[it.x];
+        const int bin = it.y, start = it.z, cnt = it.w;
+
+        if (bin < 0) continue;  // overflow tails: k_split_overflow
+
+        const int t0x = (bin % P.ntx) * P.tx, t0y = ((bin / P.ntx) % P.nty) * P.ty,
+                  t0z = (bin / (P.ntx * P.nty)) * P.tz;
+        // stage E, B: box node (a, b, c) <-> absolute node (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)
+        for (int k = tid; k < nE; k += TPB) {
+            int a = k % ex, b = (k / ex) % ey, c = k / (ex * ey);
+            int l = t0z - 1 + c;
+            l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
+            int64_t o = cell_index(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Fs[q * nE + k] = F6[q][o];
+        }
+        for (int k = tid; k < nJ; k += TPB) Js[k] = 0;
+        if (P.und_kind)
+            for (int k = tid; k < nTab; k += TPB) ext_plane(P, S.k0, t0z - 1 + k, S.t, tabA[k], tabC[k], tabS[k]);
+        __syncthreads();
+
+        const LdsBox box{Fs, nE, ex, ey};
+        const int64_t b0 = IO.in_off[bin];
+        const int end = min(cnt, start + CH);
+        for (int base = start; base < end; base += TPB) {
+            int k = base + tid;
+            bool act = k < end;
+            PState q;
+            if (act) {
+                load_particle(IO.in, b0 + k, P, q);
+                const int li = q.i - t0x, lj = q.j - t0y, lk = q.l - t0z;
+                const bool inside = li >= 0 && li < P.tx && lj >= 0 && lj < P.ty && lk >= 0 && lk < P.tz &&
+                                    q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
+                                    q.o[2] >= 0.0f && q.o[2] < 1.0f;
+                if (!inside) {
+                    // cannot happen: every binned particle was appended to the bin of its cell
+                    atomicOr(flags, DFLAG_BIN_LOST);
+                    act = false;
+                } else {
+                    float EB[6], X1[3];
+                    gather6(box, q.o, li, lj, lk, EB);
+                    if (!advance(P, EB, P.und_kind != 0, tabA[lk + 1], tabC[lk + 1], tabS[lk + 1], q, X1)) {
+                        atomicOr(flags, DFLAG_NONFINITE);
+                        act = false;
+                    } else {
+                        Esk e;
+                        esk_setup(q.o, X1, e);
+                        // LDS current boxes, origin t0 - 2: box index of offset r is lrel + r + 2
+                        esk_visit(e, q.w / (float)P.dt, [&](int c, int ra, int rb, int rc, float v) {
+                            long long iv = to_fixed(v, P.fscale, flags);
+                            int r[3];
+                            r[c] = ra;
+                            r[c == 2 ? 0 : c + 1] = rb;
+                            r[c == 0 ? 2 : c - 1] = rc;
+                            int x = li + r[0] + 2, y = lj + r[1] + 2, z = lk + r[2] + 2;
+                            int idx = c == 0   ? x + dJxx * (y + dJxy * z)
+                                      : c == 1 ? nJx + x + dJyx * (y + dJyy * z)
+                                               : nJx + nJy + x + dJzx * (y + dJzy * z);
+                            atomicAdd((unsigned long long *)&Js[idx], (unsigned long long)iv);
+                        });
+                        for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
+                        act = renormalise(P, S, q);
+                    }
+                }
+            }
+            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? q.i + P.nx * (q.j + P.ny * q.l) : 0, q.o,
+                   q.u, q.w, flags);
+        }
+        __syncthreads();
+        // flush nonzero LDS currents with global 64-bit integer atomics
+        for (int k = tid; k < nJ; k += TPB) {
+            long long v = Js[k];
+            if (v == 0) continue;
+            int c, kk = k, dx, dy;
+            if (kk < nJx) {
+                c = 0;
+                dx = dJxx;
+                dy = dJxy;
+            } else if (kk < nJx + nJy) {
+                c = 1;
+                kk -= nJx;
+                dx = dJyx;
+                dy = dJyy;
+            } else {
+                c = 2;
+                kk -= nJx + nJy;
+                dx = dJzx;
+                dy = dJzy;
+            }
+            int x = kk % dx, y = (kk / dx) % dy, z = kk / (dx * dy);
+            int l = t0z - 2 + z;
+            if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
+            int64_t o = cell_index(P, t0x - 2 + x, t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
+            long long *J = c == 0 ? Jx : (c == 1 ? Jy : Jz);
+            atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
+        }
+        __syncthreads();
+    }
+}
+
+// overflow tails of the previous step: untiled path, one particle per thread,
+// persistent grid over the tail lengths read on the device
+__global__ void __launch_bounds__(256) k_split_overflow(Params P, StepCtx S, const SpeciesIO *ios, FieldsT<float> f,
+                                                        long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
+    const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
+    for (int sp = 0; sp < 2; ++sp) {
+        const SpeciesIO &IO = ios[sp];
+        const int n = (int)min((int64_t)*IO.in_ovf, IO.in_ovf_cap);
+        for (int base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
+            int k = base + threadIdx.x;
+            bool act = k < n;
+            PState q;
+            if (act) {
+                load_particle(IO.in, IO.in_ovf_start + k, P, q);
+                act = particle_global(P, S, F6, Jx, Jy, Jz, q, flags);
+            }
+            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? q.i + P.nx * (q.j + P.ny * q.l) : 0, q.o,
+                   q.u, q.w, flags);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- rebin (no physics)
+__global__ void __launch_bounds__(ST) k_rebin(Params P, const int4 *items, const int32_t *nitems, int32_t *next,
+                                              const SpeciesIO *ios, int32_t *flags) {
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int total = *nitems;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(next, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int4 it = items[item];
+        const SpeciesIO &IO = ios[it.x];
+        const int bin = it.y, start = it.z, cnt = it.w;
+        const int64_t b0 = bin < 0 ? IO.in_ovf_start : IO.in_off[bin];
+        const int end = min(cnt, start + CH);
+        for (int base = start; base < end; base += ST) {
+            int k = base + tid;
+            bool act = k < end;
+            PState q;
+            if (act) load_particle(IO.in, b0 + k, P, q);
+            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? q.i + P.nx * (q.j + P.ny * q.l) : 0, q.o,
+                   q.u, q.w, flags);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- work list
+// items (species, bin, first particle, bin count) for every CH-chunk of every
+// non-empty bin of the input buffer, then the overflow tails (bin = -1).
+// Three kernels: per-block item counts, single-thread scan of the block
+// totals, per-block writes.  They also clear the output counters.
+__device__ inline int items_of(int n) { return (n + CH - 1) / CH; }
+
+__global__ void k_wl_count(const int64_t *off0, const int32_t *cnt0, const int64_t *off1, const int32_t *cnt1,
+                           int nbins, int64_t *part) {
+    __shared__ int64_t s[WT];
+    int e = blockIdx.x * WT + threadIdx.x;
+    int v = 0;
+    if (e < nbins) v = items_of(bin_count(off0, cnt0, e));
+    else if (e < 2 * nbins) v = items_of(bin_count(off1, cnt1, e - nbins));
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = WT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_wl_scan(int64_t *part, int nblk, const int32_t *ovf0, int64_t ocap0, const int32_t *ovf1,
+                          int64_t ocap1, int32_t *nitems, int32_t *next, int4 *items, int64_t items_cap,
+                          int32_t *clr0, int32_t *clr1) {
+    if (threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int b = 0; b < nblk; ++b) {
+        int64_t v = part[b];
+        part[b] = acc;
+        acc += v;
+    }
+    int o0 = (int)min((int64_t)*ovf0, ocap0), o1 = (int)min((int64_t)*ovf1, ocap1);
+    for (int k = 0; k < items_of(o0) && acc < items_cap; ++k) items[acc++] = make_int4(0, -1, k * CH, o0);
+    for (int k = 0; k < items_of(o1) && acc < items_cap; ++k) items[acc++] = make_int4(1, -1, k * CH, o1);
+    *nitems = (int32_t)min(acc, items_cap);
+    *next = 0;
+    *clr0 = 0;
+    *clr1 = 0;
+}
+
+__global__ void k_wl_write(const int64_t *off0, const int32_t *cnt0, const int64_t *off1, const int32_t *cnt1,
+                           int nbins, const int64_t *part, int4 *items, int64_t items_cap, int32_t *zero0,
+                           int32_t *zero1) {
+    __shared__ int64_t s[WT];
+    int e = blockIdx.x * WT + threadIdx.x;
+    int v = 0, c = 0;
+    if (e < nbins) c = bin_count(off0, cnt0, e);
+    else if (e < 2 * nbins) c = bin_count(off1, cnt1, e - nbins);
+    v = items_of(c);
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 1; k < WT; k <<= 1) {  // inclusive scan in the block
+        int64_t t = (int)threadIdx.x >= k ? s[threadIdx.x - k] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t o = part[blockIdx.x] + s[threadIdx.x] - v;
+    int sp = e < nbins ? 0 : 1, bin = e < nbins ? e : e - nbins;
+    for (int k = 0; k < v; ++k)
+        if (o + k < items_cap) items[o + k] = make_int4(sp, bin, k * CH, c);
+    if (e < nbins) zero0[e] = 0;
+    else if (e < 2 * nbins) zero1[e - nbins] = 0;
+}
+
+// in_cap0/1: how many overflow-tail particles the input buffer can hold
+static void build_worklist(Ctx &c, int cur, int64_t in_cap0, int64_t in_cap1) {
+    SplitState &X = SS(c);
+    int nb = c.P.nbins;
+    int nblk = nblocks(2 * (int64_t)nb, WT);
+    int o = cur ^ 1;
+    Store &b = X.s[0], &p = X.s[1];
+    hipLaunchKernelGGL(k_wl_count, dim3(nblk), dim3(WT), 0, c.st, b.off[cur], b.cnt[cur], p.off[cur], p.cnt[cur], nb,
+                       X.scan_part);
+    hipLaunchKernelGGL(k_wl_scan, dim3(1), dim3(64), 0, c.st, X.scan_part, nblk, b.ovf[cur], in_cap0, p.ovf[cur],
+                       in_cap1, X.nitems, X.next, X.items, X.items_cap, b.ovf[o], p.ovf[o]);
+    hipLaunchKernelGGL(k_wl_write, dim3(nblk), dim3(WT), 0, c.st, b.off[cur], b.cnt[cur], p.off[cur], p.cnt[cur], nb,
+                       X.scan_part, X.items, X.items_cap, b.cnt[o], p.cnt[o]);
+}
+
+static SpeciesIO species_io(Ctx &c, int sp, int cur, int64_t in_ovf_start) {
+    Store &s = SS(c).s[sp];
+    int o = cur ^ 1;
+    SpeciesIO io;
+    io.in = s.buf[cur];
+    io.in_off = s.off[cur];
+    io.in_cnt = s.cnt[cur];
+    io.in_ovf = s.ovf[cur];
+    io.in_ovf_start = in_ovf_start;
+    io.in_ovf_cap = in_ovf_start == 0 ? s.bin_slots + s.ovf_cap : s.ovf_cap;
+    io.out.buf = s.buf[o];
+    io.out.off = s.off[o];
+    io.out.cnt = s.cnt[o];
+    io.out.ovf = s.ovf[o];
+    io.out.bin_slots = s.bin_slots;
+    io.out.ovf_cap = s.ovf_cap;
+    return io;
+}
+
+// ---------------------------------------------------------------- setup
+static Part32 carve32(char *base, int64_t slots) {
+    Part32 p;
+    uint64_t n = (uint64_t)slots;
+    p.cell = (int32_t *)base;
+    float *f = (float *)(base + 4 * n);
+    p.ox = f;
+    p.oy = f + n;
+    p.oz = f + 2 * n;
+    p.ux = f + 3 * n;
+    p.uy = f + 4 * n;
+    p.uz = f + 5 * n;
+    p.w = f + 6 * n;
+    return p;
+}
+
+void split_setup(Ctx &c) {
+    SplitState *X = new SplitState();
+    c.split = X;
+    const Params &P = c.P;
+    char *A = c.arena;
+    int64_t nb = P.nbins;
+    for (int sp = 0; sp < 2; ++sp) {
+        Store &s = X->s[sp];
+        s.bin_slots = sp ? c.split_slots_p : c.split_slots_b;
+        s.ovf_cap = sp ? c.ovf_cap_p : c.ovf_cap_b;
+        int64_t slots = s.bin_slots + s.ovf_cap;
+        char *b = A + (sp ? c.split_off_p : c.split_off_b);
+        s.buf[0] = carve32(b, slots);
+        s.buf[1] = carve32(b + 32 * (uint64_t)slots, slots);
+    }
+    char *bins = A + c.split_off_bins;
+    int64_t *offs = (int64_t *)bins;
+    int32_t *cnts = (int32_t *)(offs + 4 * (nb + 1));
+    int32_t *ovfs = cnts + 4 * nb;
+    for (int sp = 0; sp < 2; ++sp)
+        for (int k = 0; k < 2; ++k) {
+            X->s[sp].off[k] = offs + (2 * sp + k) * (nb + 1);
+            X->s[sp].cnt[k] = cnts + (2 * sp + k) * nb;
+            X->s[sp].ovf[k] = ovfs + (2 * sp + k);
+        }
+    X->nitems = ovfs + 4;
+    X->next = ovfs + 5;
+    char *wl = A + c.split_off_wl;
+    X->items_cap = c.split_items_cap;
+    X->items = (int4 *)wl;
+    X->scan_part = (int64_t *)(wl + 16 * (uint64_t)X->items_cap);
+    X->tmpcnt = (int32_t *)(X->scan_part + nblocks(2 * nb, WT) + 8);
+    X->tmpoff = (int64_t *)(X->tmpcnt + 2 * nb + 8);
+    X->ios = (SpeciesIO *)(((uintptr_t)(X->tmpoff + nb + 8) + 15) & ~(uintptr_t)15);
+    int eb;
+    X->lds_bytes = lds_bytes_of(P, eb);
+    // launch shapes: 0 = 512 threads at 2 waves per SIMD (no spills), 1 = 384 threads at 3 waves per SIMD
+    X->tpb = c.opt.variant == 1 ? 384 : 512;
+    int waves = X->tpb / 64, max_wg_waves = c.opt.variant == 1 ? 12 : 8;
+    int per_cu = std::max(1, std::min(max_wg_waves / waves, (160 * 1024) / std::max(1, X->lds_bytes)));
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int ncu = 256;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) ncu = prop.multiProcessorCount;
+    X->grid = ncu * per_cu;
+    (void)hipFuncSetAttribute((const void *)k_split_step<512, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              X->lds_bytes);
+    (void)hipFuncSetAttribute((const void *)k_split_step<384, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              X->lds_bytes);
+    (void)hipMemsetAsync(bins, 0, c.split_bins_bytes, c.st);
+    // species descriptors (pointers only; their targets change, they do not)
+    SpeciesIO h[6] = {species_io(c, 0, 0, X->s[0].bin_slots), species_io(c, 1, 0, X->s[1].bin_slots),
+                      species_io(c, 0, 1, X->s[0].bin_slots), species_io(c, 1, 1, X->s[1].bin_slots),
+                      species_io(c, 0, 1, 0), species_io(c, 1, 1, 0)};
+    (void)hipMemcpyAsync(X->ios, h, sizeof h, hipMemcpyHostToDevice, c.st);
+    (void)hipStreamSynchronize(c.st);
+}
+
+void split_free(Ctx &c) {
+    delete static_cast<SplitState *>(c.split);
+    c.split = nullptr;
+}
+
+// ---------------------------------------------------------------- flat -> bins (init)
+// beam: lab Gaussian -> boosted frame (FP64, as in the FP64 path) -> split
+// position, appended to a flat list at the start of buffer 1
+__global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, double sy, double szl, double sux,
+                              double suy, double gB, double es, Part32 flat, int32_t *nflat, double *part) {
+    __shared__ double red[2][ST];
+    int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
+    double cnt = 0.0, vzs = 0.0;
+    bool act = false;
+    PState s;
+    if (q < n) {
+        double x = 0.5 * P.nx + sx * g[q];
+        double y = 0.5 * P.ny + sy * g[n + q];
+        double zl = szl * g[2 * n + q];
+        double ux = sux * g[3 * n + q], uy = suy * g[4 * n + q];
+        double gam = gB * (1.0 + es * g[5 * n + q]);
+        double uz = sqrt(gam * gam - 1.0 - ux * ux - uy * uy);
+        double glab = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        double zb = P.gR * zl, tb = -P.gR * P.bR * zl;
+        double uzb = P.gR * (uz - P.bR * glab);
+        double gb = sqrt(1.0 + ux * ux + uy * uy + uzb * uzb);
+        double drift = -tb;
+        x = x + ux / gb * drift;
+        y = y + uy / gb * drift;
+        double z = zb + uzb / gb * drift + P.zoff;
+        x = fmod(x, (double)P.nx);
+        if (x < 0) x += P.nx;
+        y = fmod(y, (double)P.ny);
+        if (y < 0) y += P.ny;
+        if (z >= 3.0 && z < (double)(P.nz - 4)) {
+            act = true;
+            double fx = floor(x), fy = floor(y), fz = floor(z);
+            s.i = min((int)fx, P.nx - 1);
+            s.j = min((int)fy, P.ny - 1);
+            s.l = (int)fz;
+            s.o[0] = (float)(x - fx);
+            s.o[1] = (float)(y - fy);
+            s.o[2] = (float)(z - fz);
+            for (int d = 0; d < 3; ++d)
+                if (s.o[d] >= 1.0f) s.o[d] = 0.99999994f;  // FP32 rounding of x - floor(x) up to 1
+            s.u[0] = (float)ux;
+            s.u[1] = (float)uy;
+            s.u[2] = (float)uzb;
+            s.w = (float)P.wbeam;
+            cnt = 1.0;
+            vzs = uzb / gb;
+        }
+    }
+    int r = reserve_slot(act, 0, nflat);
+    if (act) {
+        flat.cell[r] = s.i + P.nx * (s.j + P.ny * s.l);
+        flat.ox[r] = s.o[0];
+        flat.oy[r] = s.o[1];
+        flat.oz[r] = s.o[2];
+        flat.ux[r] = s.u[0];
+        flat.uy[r] = s.u[1];
+        flat.uz[r] = s.u[2];
+        flat.w[r] = s.w;
+    }
+    red[0][threadIdx.x] = cnt;
+    red[1][threadIdx.x] = vzs;
+    __syncthreads();
+    for (int h = ST / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = red[0][0];
+        part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// plasma sheets [l0, l0 + nsheets) at time t, window origin k0: appended to bins
+// of `out` (bins == true) or to a flat list counted by out.ovf (bins == false)
+__global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_t k0, OutStore out, int bins,
+                           int32_t *flags) {
+    int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
+    bool act = q < total;
+    PState s;
+    int key = 0;
+    if (act) {
+        int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
+        int64_t l = l0 + q / per;
+        int64_t r = q % per;
+        int a = (int)(r % P.ppx);
+        r /= P.ppx;
+        s.i = (int)(r % P.nx);
+        r /= P.nx;
+        int b = (int)(r % P.ppy);
+        s.j = (int)(r / P.ppy);
+        double w = sheet_weight(P, l);
+        double z = sheet_z(l, P.ppz, P.bR, t) - (double)k0;  // logical
+        double fz = floor(z);
+        s.l = (int)fz;
+        s.o[0] = (float)((a + 0.5) / P.ppx);
+        s.o[1] = (float)((b + 0.5) / P.ppy);
+        s.o[2] = (float)(z - fz);
+        if (s.o[2] >= 1.0f) s.o[2] = 0.99999994f;
+        s.u[0] = 0.0f;
+        s.u[1] = 0.0f;
+        s.u[2] = (float)(-P.uR);
+        s.w = (float)w;
+        act = w != 0.0 && s.l >= 3 && s.l < P.nz - 4;
+        key = act ? bin_of(P, s.i, s.j, s.l) : 0;
+    }
+    if (bins) {
+        append(out, act, key, act ? s.i + P.nx * (s.j + P.ny * s.l) : 0, s.o, s.u, s.w, flags);
+    } else {
+        int r = reserve_slot(act, 0, out.ovf);
+        if (act) {
+            out.buf.cell[r] = s.i + P.nx * (s.j + P.ny * s.l);
+            out.buf.ox[r] = s.o[0];
+            out.buf.oy[r] = s.o[1];
+            out.buf.oz[r] = s.o[2];
+            out.buf.ux[r] = s.u[0];
+            out.buf.uy[r] = s.u[1];
+            out.buf.uz[r] = s.u[2];
+            out.buf.w[r] = s.w;
+        }
+    }
+}
+
+__global__ void k_count_bins(Params P, Part32 flat, int64_t n, int32_t *cnt) {
+    int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
+    if (q >= n) return;
+    int cell = flat.cell[q];
+    int i = cell % P.nx, j = (cell / P.nx) % P.ny, l = cell / P.plane;
+    atomicAdd(&cnt[bin_of(P, i, j, l)], 1);
+}
+
+// bin capacities from counts with slack; host side
+static bool layout_from_counts(Ctx &c, int sp, const std::vector<int32_t> &cnt, std::vector<int64_t> &off) {
+    Store &s = SS(c).s[sp];
+    int64_t nb = c.P.nbins;
+    off.assign(nb + 1, 0);
+    int64_t total = 0;
+    for (int64_t b = 0; b < nb; ++b) total += cnt[b];
+    int64_t spare = s.bin_slots - total;
+    if (spare < 0) return false;
+    // every bin: count + 1/8 of its count + an even share of the remaining room
+    int64_t extra = 0;
+    for (int64_t b = 0; b < nb; ++b) extra += cnt[b] / 8;
+    int64_t share = std::max<int64_t>(0, (spare - extra) / std::max<int64_t>(1, nb));
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t cap = cnt[b] + (extra <= spare ? cnt[b] / 8 : 0) + share;
+        off[b + 1] = off[b] + cap;
+    }
+    return off[nb] <= s.bin_slots;
+}
+
+static pic_status upload_layout(Ctx &c, int sp, const std::vector<int64_t> &off, int which) {
+    Store &s = SS(c).s[sp];
+    PIC_HIP(c, hipMemcpyAsync(s.off[which], off.data(), 8 * off.size(), hipMemcpyHostToDevice, c.st));
+    return PIC_OK;
+}
+
+// layout both buffers from the flat lists held in buffer 1 (counts in ovf[1]),
+// then move them into the bins of buffer 0
+static pic_status bins_from_flat(Ctx &c) {
+    SplitState &X = SS(c);
+    const Params &P = c.P;
+    int64_t nb = P.nbins;
+    std::vector<int32_t> nflat(2);
+    for (int sp = 0; sp < 2; ++sp)
+        PIC_HIP(c, hipMemcpyAsync(&nflat[sp], X.s[sp].ovf[1], 4, hipMemcpyDeviceToHost, c.st));
+    PIC_HIP(c, hipMemsetAsync(X.tmpcnt, 0, 8 * nb, c.st));
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    for (int sp = 0; sp < 2; ++sp)
+        if (nflat[sp] > 0)
+            hipLaunchKernelGGL(k_count_bins, dim3(nblocks(nflat[sp], ST)), dim3(ST), 0, c.st, P, X.s[sp].buf[1],
+                               (int64_t)nflat[sp], X.tmpcnt + sp * nb);
+    std::vector<int32_t> h(2 * nb);
+    PIC_HIP(c, hipMemcpyAsync(h.data(), X.tmpcnt, 8 * nb, hipMemcpyDeviceToHost, c.st));
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    for (int sp = 0; sp < 2; ++sp) {
+        std::vector<int32_t> cs(h.begin() + sp * nb, h.begin() + (sp + 1) * nb);
+        std::vector<int64_t> off;
+        if (!layout_from_counts(c, sp, cs, off)) {
+            c.err = "split layout: particle capacity exceeded";
+            return PIC_ENOMEM;
+        }
+        pic_status s = upload_layout(c, sp, off, 0);
+        if (s == PIC_OK) s = upload_layout(c, sp, off, 1);
+        if (s != PIC_OK) return s;
+        // the flat list is the "overflow" of buffer 1: no bin entries
+        PIC_HIP(c, hipMemsetAsync(X.s[sp].cnt[1], 0, 4 * nb, c.st));
+        X.s[sp].n_flat = nflat[sp];
+    }
+    // the flat lists are read as overflow tails that start at slot 0 and may fill the whole buffer
+    build_worklist(c, 1, X.s[0].bin_slots + X.s[0].ovf_cap, X.s[1].bin_slots + X.s[1].ovf_cap);
+    hipLaunchKernelGGL(k_rebin, dim3(X.grid), dim3(ST), 0, c.st, P, X.items, X.nitems, X.next, X.ios + 4, c.dflags);
+    for (int sp = 0; sp < 2; ++sp) PIC_HIP(c, hipMemsetAsync(X.s[sp].ovf[1], 0, 4, c.st));
+    c.cur32 = 0;
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    return PIC_OK;
+}
+
+void split_beam_init(Ctx &c, const double *normals_dev) {
+    SplitState &X = SS(c);
+    const Params &P = c.P;
+    int64_t n = c.beam.n_macro;
+    double D = c.grid.dx_m;
+    double F = c.beam.gamma_lab / (c.beam.gamma_lab * P.gR - sqrt(c.beam.gamma_lab * c.beam.gamma_lab - 1.0) *
+                                                                   sqrt(P.gR * P.gR - 1.0));
+    int nblk = nblocks(n, ST);
+    hipLaunchKernelGGL(k_beam_init32, dim3(nblk), dim3(ST), 0, c.st, P, normals_dev, n, c.beam.sigma_cells[0],
+                       c.beam.sigma_cells[1], c.beam.sigma_cells[2] / F, c.beam.emit_n_m[0] / (c.beam.sigma_cells[0] * D),
+                       c.beam.emit_n_m[1] / (c.beam.sigma_cells[1] * D), c.beam.gamma_lab, c.beam.rel_energy_spread_rms,
+                       X.s[0].buf[1], X.s[0].ovf[1], c.red);
+    std::vector<double> h(2 * (size_t)nblk);
+    (void)hipMemcpyAsync(h.data(), c.red, 16 * (uint64_t)nblk, hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    double cnt = 0, vz = 0;
+    for (int k = 0; k < nblk; ++k) {
+        cnt += h[2 * k];
+        vz += h[2 * k + 1];
+    }
+    c.bw = cnt > 0 ? vz / cnt : 0.0;
+}
+
+pic_status split_plasma_fill(Ctx &c) {
+    SplitState &X = SS(c);
+    const Params &P = c.P;
+    if (P.has_plasma) {
+        int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
+        int64_t total = (c.sh_hi - c.sh_lo) * per;
+        OutStore o;
+        o.buf = X.s[1].buf[1];
+        o.off = X.s[1].off[1];
+        o.cnt = X.s[1].cnt[1];
+        o.ovf = X.s[1].ovf[1];
+        o.bin_slots = X.s[1].bin_slots;
+        o.ovf_cap = X.s[1].ovf_cap;
+        if (total > 0)
+            hipLaunchKernelGGL(k_inject32, dim3(nblocks(total, ST)), dim3(ST), 0, c.st, P, c.sh_lo, total, 0.0,
+                               (int64_t)0, o, 0, c.dflags);
+    }
+    return bins_from_flat(c);
+}
+
+// ---------------------------------------------------------------- the step
+void split_step(Ctx &c, const StepCtx &S) {
+    SplitState &X = SS(c);
+    const Params &P = c.P;
+    FieldsT<float> f;
+    for (int k = 0; k < 3; ++k) {
+        f.E[k] = c.E32[k];
+        f.B[k] = c.B32[k];
+    }
+    int cur = c.cur32;
+    hipEvent_t t0 = timing_begin(c);
+    launch_bhalf<float>(P, S.k0r, f, (float)(0.5 * P.dt), nullptr, c.st);
+    timing_end(c, 1, t0);
+    hipEvent_t t1 = timing_begin(c);
+    build_worklist(c, cur, 0, 0);  // overflow tails go to k_split_overflow
+    timing_end(c, 2, t1);
+    hipEvent_t t2 = timing_begin(c);
+    if (X.tpb == 384)
+        hipLaunchKernelGGL((k_split_step<384, 3>), dim3(X.grid), dim3(384), X.lds_bytes, c.st, P, S, X.items,
+                           X.nitems, X.next, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1], c.Ji[2], c.dflags);
+    else
+        hipLaunchKernelGGL((k_split_step<512, 2>), dim3(X.grid), dim3(512), X.lds_bytes, c.st, P, S, X.items,
+                           X.nitems, X.next, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1], c.Ji[2], c.dflags);
+    hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1],
+                       c.Ji[2], c.dflags);
+    timing_end(c, 0, t2);
+    hipEvent_t t3 = timing_begin(c);
+    if (P.ions) launch_ion_fixed(P, c.sh_lo, c.sh_hi - c.sh_lo, S.t, S.t1, S.k0, c.jioni, c.dflags, c.st);
+    timing_end(c, 2, t3);
+    hipEvent_t t4 = timing_begin(c);
+    launch_bhalf<float>(P, S.k0r, f, (float)(0.5 * P.dt), (float *)c.murbuf, c.st);
+    launch_eupdate<float, long long>(P, S.k0r, f, c.Ji, c.jioni, (float)P.dt, c.st);
+    launch_mur_shift<float, long long>(P, S.k0r, S.shift, f, (const float *)c.murbuf, c.jioni, (float)P.dt, c.st);
+    timing_end(c, 1, t4);
+}
+
+// inject sheets [l0, l1) at time t into the output buffer (after split_step), then swap
+void split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n) {
+    SplitState &X = SS(c);
+    const Params &P = c.P;
+    int o = c.cur32 ^ 1;
+    if (P.has_plasma && l1 > l0) {
+        int64_t total = (l1 - l0) * (int64_t)P.plane * P.ppx * P.ppy;
+        OutStore out;
+        out.buf = X.s[1].buf[o];
+        out.off = X.s[1].off[o];
+        out.cnt = X.s[1].cnt[o];
+        out.ovf = X.s[1].ovf[o];
+        out.bin_slots = X.s[1].bin_slots;
+        out.ovf_cap = X.s[1].ovf_cap;
+        hipLaunchKernelGGL(k_inject32, dim3(nblocks(total, ST)), dim3(ST), 0, c.st, P, l0, total, t, k0n, out, 1,
+                           c.dflags);
+    }
+    c.cur32 = o;
+}
+
+// periodic host check: re-lay out the bins when any overflowed or is nearly full
+pic_status split_check(Ctx &c) {
+    SplitState &X = SS(c);
+    const Params &P = c.P;
+    int64_t nb = P.nbins;
+    int cur = c.cur32;
+    std::vector<int32_t> h(2 * nb);
+    std::vector<int64_t> off(2 * (nb + 1));
+    int32_t ov[2];
+    for (int sp = 0; sp < 2; ++sp) {
+        PIC_HIP(c, hipMemcpyAsync(h.data() + sp * nb, X.s[sp].cnt[cur], 4 * nb, hipMemcpyDeviceToHost, c.st));
+        PIC_HIP(c, hipMemcpyAsync(off.data() + sp * (nb + 1), X.s[sp].off[cur], 8 * (nb + 1), hipMemcpyDeviceToHost, c.st));
+        PIC_HIP(c, hipMemcpyAsync(&ov[sp], X.s[sp].ovf[cur], 4, hipMemcpyDeviceToHost, c.st));
+    }
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    bool need = false;
+    for (int sp = 0; sp < 2; ++sp) {
+        if (ov[sp] > 0) need = true;
+        for (int64_t b = 0; b < nb && !need; ++b) {
+            int64_t cap = off[sp * (nb + 1) + b + 1] - off[sp * (nb + 1) + b];
+            if ((int64_t)h[sp * nb + b] * 16 > cap * 15 && cap > 0) need = true;
+        }
+    }
+    if (!need) return PIC_OK;
+    // new layout from the true counts (bin counts clipped to capacity + overflow re-binned below)
+    // count per destination bin including overflow particles: count kernel over the overflow tails
+    PIC_HIP(c, hipMemsetAsync(X.tmpcnt, 0, 8 * nb, c.st));
+    for (int sp = 0; sp < 2; ++sp) {
+        int n = std::min<int64_t>(ov[sp], X.s[sp].ovf_cap);
+        if (n > 0) {
+            Part32 t = X.s[sp].buf[cur];
+            Part32 v;
+            int64_t s0 = X.s[sp].bin_slots;
+            v.cell = t.cell + s0;
+            v.ox = t.ox + s0;
+            v.oy = t.oy + s0;
+            v.oz = t.oz + s0;
+            v.ux = t.ux + s0;
+            v.uy = t.uy + s0;
+            v.uz = t.uz + s0;
+            v.w = t.w + s0;
+            hipLaunchKernelGGL(k_count_bins, dim3(nblocks(n, ST)), dim3(ST), 0, c.st, P, v, (int64_t)n,
+                               X.tmpcnt + sp * nb);
+        }
+    }
+    std::vector<int32_t> extra(2 * nb);
+    PIC_HIP(c, hipMemcpyAsync(extra.data(), X.tmpcnt, 8 * nb, hipMemcpyDeviceToHost, c.st));
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    int o = cur ^ 1;
+    std::vector<std::vector<int64_t>> lay(2);
+    for (int sp = 0; sp < 2; ++sp) {
+        std::vector<int32_t> cs(nb);
+        for (int64_t b = 0; b < nb; ++b) {
+            int64_t cap = off[sp * (nb + 1) + b + 1] - off[sp * (nb + 1) + b];
+            cs[b] = (int32_t)std::min<int64_t>(h[sp * nb + b], cap) + extra[sp * nb + b];
+        }
+        if (!layout_from_counts(c, sp, cs, lay[sp])) {
+            c.err = "split re-layout: particle capacity exceeded";
+            return PIC_ENOMEM;
+        }
+        pic_status s = upload_layout(c, sp, lay[sp], o);
+        if (s != PIC_OK) return s;
+    }
+    build_worklist(c, cur, X.s[0].ovf_cap, X.s[1].ovf_cap);
+    hipLaunchKernelGGL(k_rebin, dim3(X.grid), dim3(ST), 0, c.st, P, X.items, X.nitems, X.next, X.ios + 2 * cur,
+                       c.dflags);
+    for (int sp = 0; sp < 2; ++sp) {
+        pic_status s = upload_layout(c, sp, lay[sp], cur);
+        if (s != PIC_OK) return s;
+    }
+    c.cur32 = o;
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------- read-back
+// one block per bin (plus one for the overflow tail): FP64 absolute coordinates
+__global__ void k_split_out(Params P, int64_t k0, Part32 in, const int64_t *off, const int32_t *cnt, int64_t ovf_start,
+                            int32_t ovf_n, const int64_t *pref, int nbins, double *dst, int64_t stride, int nout,
+                            int32_t *alive) {
+    int b = blockIdx.x;
+    int64_t s0, n;
+    if (b < nbins) {
+        s0 = off[b];
+        int64_t cap = off[b + 1] - off[b];
+        n = cnt[b] < cap ? cnt[b] : cap;
+    } else {
+        s0 = ovf_start;
+        n = ovf_n;
+    }
+    int64_t d0 = pref[b];
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        int64_t s = s0 + k, d = d0 + k;
+        if (alive) {
+            alive[d] = 1;
+            continue;
+        }
+        int cell = in.cell[s];
+        int i = cell % P.nx, j = (cell / P.nx) % P.ny, l = cell / P.plane;
+        double v[7] = {i + (double)in.ox[s], j + (double)in.oy[s], (double)(k0 + l) + (double)in.oz[s],
+                       (double)in.ux[s], (double)in.uy[s], (double)in.uz[s], (double)in.w[s]};
+        for (int q = 0; q < nout; ++q) dst[q * stride + d] = v[q];
+    }
+}
+
+// charge of split particles on the nodes (q = -1), FP64 atomics into rho (ring order)
+__global__ void k_split_rho(Params P, int64_t k0, int k0r, Part32 in, const int64_t *off, const int32_t *cnt,
+                            int64_t ovf_start, int32_t ovf_n, int nbins, double *rho) {
+    int b = blockIdx.x;
+    int64_t s0, n;
+    if (b < nbins) {
+        s0 = off[b];
+        int64_t cap = off[b + 1] - off[b];
+        n = cnt[b] < cap ? cnt[b] : cap;
+    } else {
+        s0 = ovf_start;
+        n = ovf_n;
+    }
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        int64_t s = s0 + k;
+        int cell = in.cell[s];
+        int i = cell % P.nx, j = (cell / P.nx) % P.ny, l = cell / P.plane;
+        float o[3] = {in.ox[s], in.oy[s], in.oz[s]};
+        double w[3][3];
+        int lo[3];
+        const int base[3] = {i, j, l};
+        for (int d = 0; d < 3; ++d) {
+            int nn = o[d] >= 0.5f ? 1 : 0;
+            weights3<double>((double)o[d] - nn, w[d]);
+            lo[d] = base[d] + nn - 1;
+        }
+        double qw = -(double)in.w[s];
+        for (int c = 0; c < 3; ++c) {
+            int p = ring_plane(lo[2] + c, k0r, P.nz);
+            for (int bb = 0; bb < 3; ++bb)
+                for (int a = 0; a < 3; ++a)
+                    atomicAdd(&rho[cell_index(P, lo[0] + a, lo[1] + bb, p)], qw * w[0][a] * w[1][bb] * w[2][c]);
+        }
+    }
+}
+
+__global__ void k_split_kin(Params P, Part32 in, const int64_t *off, const int32_t *cnt, int64_t ovf_start,
+                            int32_t ovf_n, int nbins, double *part) {
+    __shared__ double s[2][256];
+    int b = blockIdx.x;
+    int64_t s0, n;
+    if (b < nbins) {
+        s0 = off[b];
+        int64_t cap = off[b + 1] - off[b];
+        n = cnt[b] < cap ? cnt[b] : cap;
+    } else {
+        s0 = ovf_start;
+        n = ovf_n;
+    }
+    double v0 = 0, v1 = 0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) {
+        int64_t q = s0 + k;
+        double ux = in.ux[q], uy = in.uy[q], uz = in.uz[q];
+        v0 += 1.0;
+        v1 += (double)in.w[q] * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+    }
+    s[0][threadIdx.x] = v0;
+    s[1][threadIdx.x] = v1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + h];
+            s[1][threadIdx.x] += s[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * b] = s[0][0];
+        part[2 * b + 1] = s[1][0];
+    }
+}
+
+// prefix offsets (host) of the valid particles of each bin (+ overflow) of species sp
+static int64_t split_prefix(Ctx &c, int sp, int32_t &ovf_n) {
+    SplitState &X = SS(c);
+    int64_t nb = c.P.nbins;
+    Store &s = X.s[sp];
+    int cur = c.cur32;
+    std::vector<int32_t> h(nb);
+    std::vector<int64_t> off(nb + 1), pref(nb + 2);
+    (void)hipMemcpyAsync(h.data(), s.cnt[cur], 4 * nb, hipMemcpyDeviceToHost, c.st);
+    (void)hipMemcpyAsync(off.data(), s.off[cur], 8 * (nb + 1), hipMemcpyDeviceToHost, c.st);
+    (void)hipMemcpyAsync(&ovf_n, s.ovf[cur], 4, hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    ovf_n = (int32_t)std::min<int64_t>(ovf_n, s.ovf_cap);
+    pref[0] = 0;
+    for (int64_t b = 0; b < nb; ++b) pref[b + 1] = pref[b] + std::min<int64_t>(h[b], off[b + 1] - off[b]);
+    pref[nb + 1] = pref[nb] + ovf_n;
+    (void)hipMemcpyAsync(X.tmpoff, pref.data(), 8 * (nb + 2), hipMemcpyHostToDevice, c.st);
+    return pref[nb + 1];
+}
+
+void split_read(Ctx &c, int sp, double *dst7, int32_t *alive, int64_t *n) {
+    SplitState &X = SS(c);
+    int32_t ovf_n = 0;
+    int64_t tot = split_prefix(c, sp, ovf_n);
+    *n = tot;
+    if ((!dst7 && !alive) || tot == 0) return;
+    Store &s = X.s[sp];
+    int cur = c.cur32;
+    hipLaunchKernelGGL(k_split_out, dim3(c.P.nbins + 1), dim3(256), 0, c.st, c.P, c.k0, s.buf[cur], s.off[cur],
+                       s.cnt[cur], s.bin_slots, ovf_n, X.tmpoff, c.P.nbins, dst7, tot, 7, alive);
+}
+
+int64_t split_beam_to64(Ctx &c, double *dst6) {
+    SplitState &X = SS(c);
+    int32_t ovf_n = 0;
+    int64_t tot = split_prefix(c, 0, ovf_n);
+    if (tot == 0) return 0;
+    Store &s = X.s[0];
+    int cur = c.cur32;
+    int64_t stride = std::max<int64_t>(c.beam.n_macro, 1);
+    if (tot > stride) tot = stride;  // cannot happen: beam particles are never created
+    hipLaunchKernelGGL(k_split_out, dim3(c.P.nbins + 1), dim3(256), 0, c.st, c.P, c.k0, s.buf[cur], s.off[cur],
+                       s.cnt[cur], s.bin_slots, ovf_n, X.tmpoff, c.P.nbins, dst6, stride, 6, (int32_t *)nullptr);
+    return tot;
+}
+
+void split_rho(Ctx &c, double *rho) {
+    SplitState &X = SS(c);
+    int cur = c.cur32;
+    for (int sp = 0; sp < 2; ++sp) {
+        Store &s = X.s[sp];
+        int32_t ovf_n = 0;
+        (void)hipMemcpyAsync(&ovf_n, s.ovf[cur], 4, hipMemcpyDeviceToHost, c.st);
+        (void)hipStreamSynchronize(c.st);
+        ovf_n = (int32_t)std::min<int64_t>(ovf_n, s.ovf_cap);
+        hipLaunchKernelGGL(k_split_rho, dim3(c.P.nbins + 1), dim3(256), 0, c.st, c.P, c.k0, (int)(c.k0 % c.P.nz),
+                           s.buf[cur], s.off[cur], s.cnt[cur], s.bin_slots, ovf_n, c.P.nbins, rho);
+    }
+}
+
+void split_plasma_kinetic(Ctx &c, double *out2) {
+    SplitState &X = SS(c);
+    int cur = c.cur32;
+    Store &s = X.s[1];
+    int32_t ovf_n = 0;
+    (void)hipMemcpyAsync(&ovf_n, s.ovf[cur], 4, hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    ovf_n = (int32_t)std::min<int64_t>(ovf_n, s.ovf_cap);
+    int nblk = c.P.nbins + 1;
+    hipLaunchKernelGGL(k_split_kin, dim3(nblk), dim3(256), 0, c.st, c.P, s.buf[cur], s.off[cur], s.cnt[cur],
+                       s.bin_slots, ovf_n, c.P.nbins, c.red);
+    std::vector<double> h(2 * (size_t)nblk);
+    (void)hipMemcpyAsync(h.data(), c.red, 16 * (uint64_t)nblk, hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    out2[0] = out2[1] = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        out2[0] += h[2 * b];
+        out2[1] += h[2 * b + 1];
+    }
+}
+
+}  // namespace pic

@@ -1,0 +1,115 @@
+"""CPU checks of the C-ABI boundary: the library loads and exports every
+symbol include/pic.h declares, the ctypes mirror has the C compiler's struct
+layout, host-side constants agree with the oracle's independent derivation,
+and invalid configurations are rejected.  No GPU call is made."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import picinputs as pin
+from oracle import pyoracle as po
+from paper_2411_04703_amd import abi, sim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+
+pytestmark = pytest.mark.usefixtures("oracle_built")
+
+
+def test_library_exports_every_declared_symbol():
+    names = re.findall(r"^PIC_API [^(]*?\b(pic_\w+)\(", open(HEADER).read(), flags=re.M)
+    assert len(names) >= 15
+    L = abi.load()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(abi.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", abi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(names) <= exported
+    assert not [s for s in exported if s.startswith("_ZN3pic")], "internal symbols leak"
+
+
+STRUCTS = ["pic_grid", "pic_frame", "pic_beam", "pic_plasma", "pic_undulator", "pic_options", "pic_layout",
+           "pic_derived", "pic_diag_out"]
+
+
+def test_ctypes_mirror_matches_c_layout(tmp_path):
+    src = tmp_path / "sz.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
+    for s in STRUCTS:
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f, _ in getattr(abi, s)._fields_:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for s in STRUCTS:
+        cls = getattr(abi, s)
+        assert int(got[s]) == C.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3, 4])
+def test_derived_constants_match_oracle(idx):
+    w = pin.workload(idx)
+    d = sim.derive(w)
+    tiny = pin.scaled(w, nx=4, ny=4, nz=16)  # constants do not depend on the grid size
+    o = po.Sim(pin.scaled(tiny, n_beam=0), pin.beam_normals(0)).info()
+    assert d["z_offset_cells"] == w["beam"]["z_center_cells"]
+    for k_lib, k_orc in (("dt", "dt"), ("gamma_R", "gR"), ("beta_R", "bR"), ("u_R", "uR"), ("n_ref_m3", "nref_m3"),
+                         ("n0_norm", "n0n"), ("k_u_lab", "ku"), ("B0_norm", "B0")):
+        a, b = d[k_lib], getattr(o, k_orc)
+        assert a == pytest.approx(b, rel=1e-14, abs=1e-300), (k_lib, a, b)
+    o2 = po.Sim(pin.scaled(tiny, n_beam=16), pin.beam_normals(16)).info()
+    assert d["elongation"] == pytest.approx(o2.F_elong, rel=1e-13)
+    assert d["sigma_z_lab_cells"] == pytest.approx(o2.sig_zlab, rel=1e-13)
+    # beam weight scales as 1 / n_macro
+    assert d["w_beam"] * w["beam"]["n_macro"] == pytest.approx(o2.wbeam * 16, rel=1e-13)
+    assert 20 <= d["frac_bits"] <= 56
+
+
+def test_layout_scales_with_capacity():
+    w = pin.workload(1)
+    a = sim.query_layout(w, precision=abi.PIC_FP64_PLAIN, max_steps=64)
+    b = sim.query_layout(w, precision=abi.PIC_FP64_PLAIN, max_steps=64, record=1)
+    assert a.arena_bytes > 0 and b.arena_bytes > 0 and a.state_bytes > 0
+    assert a.plasma_capacity >= 128 * 128 * 2 * (512 - 7)
+    assert a.beam_capacity == 4_194_304
+
+
+@pytest.mark.parametrize("mutate,expect", [
+    (lambda w: w["grid"].update(nz=8), abi.PIC_EINVAL),
+    (lambda w: w["grid"].update(cfl=1.5), abi.PIC_EINVAL),
+    (lambda w: w["frame"].update(gamma_boost=0.5), abi.PIC_EINVAL),
+    (lambda w: w["undulator"].update(kind=1, period_lab_m=0.0), abi.PIC_EINVAL),
+    (lambda w: w["plasma"].update(n0_lab_cm3=1e16, ppc=[0, 1, 2]), abi.PIC_EINVAL),
+    (lambda w: w["beam"].update(sigma_cells=[0.0, 1.0, 1.0]), abi.PIC_EINVAL),
+])
+def test_invalid_configurations_are_rejected(mutate, expect):
+    w = pin.workload(0)
+    mutate(w)
+    with pytest.raises(abi.PicError) as e:
+        sim.query_layout(w)
+    assert e.value.status == expect
+
+
+def test_frac_bits_range_error():
+    with pytest.raises(abi.PicError) as e:
+        sim.query_layout(pin.workload(1), frac_bits=62)
+    assert e.value.status == abi.PIC_ERANGE
+
+
+def test_gpu_entry_points_fail_loudly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    w = pin.scaled(pin.workload(0), n_beam=16)
+    with pytest.raises(RuntimeError):
+        sim.Sim(w, pin.beam_normals(16))

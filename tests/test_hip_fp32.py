@@ -1,0 +1,169 @@
+"""GPU tests of the FP32 split-precision path (int32 cell + FP32 offset, FP32
+fields, 64-bit fixed-point current).
+
+Tolerances (stated here, derived from the arithmetic):
+* positions are stored as FP32 offsets in a cell, so an absolute coordinate
+  carries an error of about 2^-24 cells per step of rounding; after N steps
+  of a smooth beam the moments agree with FP64 to ~1e-6 relative and the
+  bunching factor to ~1e-6 absolute.  The bar for beam moments and |b| after
+  a full run is 1e-3 relative (1e-4 absolute for |b|), well above the FP32
+  noise floor and far below any physical effect;
+* fields carry FP32 rounding of the FDTD update plus 2^-f fixed-point
+  quantisation of the current: L2 error 1e-4 of the whole field's magnitude
+  against FP64 (a small component inherits the rounding of the large ones).
+* the current is a sum of integers, so everything the step produces is
+  bitwise reproducible, also under a permutation of the particles."""
+import math
+
+import numpy as np
+import pytest
+
+import picinputs as pin
+from oracle import pyoracle as po
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_built")]
+
+FIELDS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+
+
+def _w(name):
+    if name == "undulator_beam":
+        return pin.workload(0)
+    if name == "beam_plasma_ions":
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=8192, sigma=(2, 2, 8))
+        w["beam"]["charge_C"] = 3e-9
+        return w
+    if name == "adjoint_sub":
+        w = pin.adjoint_subcase()
+        w["undulator"]["z_start_lab_m"] = w["frame"]["gamma_boost"] * 20 * w["grid"]["dx_m"]
+        return w
+    raise KeyError(name)
+
+
+def _sims(w, seed=0, **kw):
+    from paper_2411_04703_amd.sim import Sim
+    nrm = pin.beam_normals(w["beam"]["n_macro"], seed)
+    ref = po.Sim(w, nrm)
+    w = pin.scaled(w)
+    w["frame"]["window_beta"] = ref.info().bw
+    s32 = Sim(w, nrm, precision=1, **kw)
+    s64 = Sim(w, nrm, precision=0, max_steps=400)
+    return ref, s32, s64, w, nrm
+
+
+def _sorted(p):
+    """particles as rows sorted lexicographically by position (order-free comparison)"""
+    al = p["alive"] == 1
+    a = np.stack([p[k][al] for k in ("z", "y", "x", "uz", "uy", "ux", "w")], axis=1)
+    return a[np.lexsort(a.T[::-1])]
+
+
+@pytest.mark.parametrize("case", ["undulator_beam", "beam_plasma_ions"])
+def test_fp32_init_matches_fp64(case):
+    _, s32, s64, w, _ = _sims(_w(case))
+    for sp in (0, 1):
+        a, b = _sorted(s32.particles(sp)), _sorted(s64.particles(sp))
+        assert a.shape == b.shape, (sp, a.shape, b.shape)
+        if a.size:
+            np.testing.assert_allclose(a[:, :3], b[:, :3], atol=2e-5)  # positions: FP32 offsets near 1e3 cells
+            np.testing.assert_allclose(a[:, 3:6], b[:, 3:6], rtol=1e-6, atol=1e-7)
+    d32, d64 = s32.diag(), s64.diag()
+    assert d32["n_beam"] == d64["n_beam"] and d32["n_plasma"] == d64["n_plasma"]
+
+
+@pytest.mark.parametrize("case", ["undulator_beam", "beam_plasma_ions", "adjoint_sub"])
+def test_fp32_steps_track_fp64(case):
+    ref, s32, s64, w, _ = _sims(_w(case))
+    for n in (1, 5, 20):
+        k = n - int(s32.diag()["step"])
+        s32.step(k)
+        s64.step(k)
+        i = ref.info()
+        gross = i.dt * i.gR * i.n0n * i.bR * math.sqrt(ref.nc) if i.n0n else 0.0
+        f64 = {f: s64.field(f) for f in FIELDS}
+        total = math.sqrt(sum(np.linalg.norm(v) ** 2 for v in f64.values()))
+        for f in FIELDS:
+            a, b = s32.field(f), f64[f]
+            # FP32 rounds every component relative to the whole field's magnitude
+            scale = max(np.linalg.norm(b), total, gross, 1e-30)
+            assert np.linalg.norm(a - b) <= 1e-4 * scale, (n, f, np.linalg.norm(a - b) / scale)
+        d32, d64 = s32.diag(), s64.diag()
+        assert d32["n_beam"] == d64["n_beam"] and d32["n_plasma"] == d64["n_plasma"], n
+        for k2 in ("mean", "sigma", "usigma", "emit"):
+            np.testing.assert_allclose(d32[k2], d64[k2], rtol=1e-4, err_msg=(n, k2))
+        assert abs(d32["b1_abs"] - d64["b1_abs"]) < 1e-5
+
+
+def test_fp32_full_run_workload0_against_oracle():
+    """End-of-run beam moments and bunching of the 100-step undulator workload."""
+    w = pin.workload(0)
+    ref, s32, _, _, _ = _sims(w)
+    ref.step(w["steps"])
+    s32.step(w["steps"])
+    do, dg = ref.diag(2 * math.pi / 20), s32.diag()
+    for k in ("mean", "sigma", "umean", "usigma", "emit"):
+        np.testing.assert_allclose(dg[k], do[k], rtol=1e-3, atol=1e-9, err_msg=k)
+    assert abs(dg["b1_abs"] - do["b1_abs"]) < 1e-4
+    assert abs(dg["b2_abs"] - do["b2_abs"]) < 1e-4
+    assert dg["n_beam"] == do["n_beam_alive"]
+
+
+def test_fp32_is_bitwise_reproducible_and_order_free():
+    from paper_2411_04703_amd.sim import Sim
+    w = _w("beam_plasma_ions")
+    w["frame"]["window_beta"] = 0.98
+    n = w["beam"]["n_macro"]
+    nrm = pin.beam_normals(n, 5)
+    perm = pin.permutation(n, 1)
+    runs = []
+    for normals, check_every in ((nrm, 64), (nrm, 64), (nrm[:, perm], 3)):
+        s = Sim(w, np.ascontiguousarray(normals), precision=1, check_every=check_every)
+        s.step(17)
+        runs.append((s, {f: s.field(f) for f in FIELDS}))
+    for s, fields in runs[1:]:
+        for f in FIELDS:
+            assert np.array_equal(fields[f], runs[0][1][f]), f
+        for sp in (0, 1):
+            assert np.array_equal(_sorted(s.particles(sp)), _sorted(runs[0][0].particles(sp))), sp
+
+
+def test_fp32_gauss_drift_and_loading():
+    from paper_2411_04703_amd import abi
+    _, s32, _, w, _ = _sims(_w("beam_plasma_ions"))
+    d0 = s32.diag(abi.PIC_DIAG_GAUSS)
+    drift = []
+    for _ in range(6):
+        s32.step(4)
+        drift.append(s32.diag(abi.PIC_DIAG_GAUSS)["gauss_drift"])
+    # FP32 fields and offsets: the residual moves at FP32 round-off of the gross charge density
+    assert max(drift) < 1e-5 * d0["rho_max"], (drift, d0["rho_max"])
+
+
+def test_fp32_plasma_lattice_density():
+    _, s32, _, w, _ = _sims(_w("beam_plasma_ions"))
+    p = s32.particles(1)
+    g = w["frame"]["gamma_boost"]
+    assert np.all(p["uz"] == np.float32(-math.sqrt(g * g - 1)))
+    d = s32.diag()
+    cells_active = (64 - 7) * 16 * 16
+    assert d["n_plasma"] == cells_active * 2
+
+
+def test_fp32_bins_overflow_and_relayout_keep_results():
+    """A window slower than the beam makes the beam stream into bins sized for
+    plasma only: their excess goes to the overflow tail (untiled path) and the
+    periodic check re-lays the bins out.  The result equals a run whose checks
+    never fire (all excess handled by the overflow path) bit for bit."""
+    from paper_2411_04703_amd.sim import Sim
+    w = _w("beam_plasma_ions")
+    w["frame"]["window_beta"] = 0.5
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 6)
+    a = Sim(w, nrm, precision=1, check_every=2)
+    b = Sim(w, nrm, precision=1, check_every=10000)
+    a.step(24)
+    b.step(24)
+    for f in FIELDS:
+        assert np.array_equal(a.field(f), b.field(f)), f
+    for sp in (0, 1):
+        assert np.array_equal(_sorted(a.particles(sp)), _sorted(b.particles(sp))), sp
+    assert a.diag()["n_beam"] == b.diag()["n_beam"] > 0

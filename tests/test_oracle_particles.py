@@ -264,7 +264,7 @@ def test_cold_plasma_frequency_is_frame_invariant():
     for gR in (1.0001, 5.0, 20.0):
         s = _sim(2, 2, 8, plasma={"ppc": [1, 1, 2]}, gR=gR)
         i = s.info()
-        p = s.particles(1)
+        p = s.particles(1, view=True)
         A = 1e-6
         p["ux"][:] = A
         us = []
@@ -280,7 +280,7 @@ def test_cold_plasma_frequency_is_frame_invariant():
 
 def test_bunching_factor_lattice_and_uniform():
     s = _sim(8, 8, 64, n_beam=4096, bc_z=1)
-    p = s.particles(0)
+    p = s.particles(0, view=True)
     rng = np.random.default_rng(9)
     p["z"][:] = 5.0 + 20.0 * rng.integers(0, 3, p["z"].size)
     p["alive"][:] = 1
