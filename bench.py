@@ -61,6 +61,26 @@ def cpu_baseline(seconds_budget: float = 20.0) -> dict:
                       f"particles, {steps} steps, single-threaded FP64 C"}
 
 
+def copy_calibration(mib: int):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings calibrate
+    the HBM-traffic counters of the particle kernel."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_mib": mib, "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "ms": dt * 1e3, "GBps_read_plus_write": 8 * n / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,8 +89,16 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path (speedup and error)")
-    ap.add_argument("--variant", type=int, default=0, help="FP32 particle-kernel launch shape (0 or 1)")
+    ap.add_argument("--variant", type=int, default=0, help="FP32 current-deposit variant (0, 1 or 2)")
+    ap.add_argument("--tile", default="0,0,0", help="FP32 cell tile nx,ny,nz (0,0,0: the library's choice)")
+    ap.add_argument("--wg-per-cu", type=int, default=0, help="FP32 particle-kernel workgroups per CU (0 = max)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only time a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    tile = tuple(int(v) for v in args.tile.split(","))
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -89,7 +117,7 @@ def main():
     def run(precision):
         opts = dict(precision=precision)
         if precision == abi.PIC_FP32_SPLIT:
-            opts["variant"] = args.variant
+            opts.update(variant=args.variant, tile=tile, wg_per_cu=args.wg_per_cu)
         if precision == abi.PIC_FP64_PLAIN:
             opts["max_steps"] = 64
         sim = Sim(w, nrm, **opts)
@@ -111,6 +139,8 @@ def main():
         return wall, ms, launches, n_active, d1
 
     prec = abi.PIC_FP32_SPLIT if args.precision == "fp32" else abi.PIC_FP64_PLAIN
+    from paper_2411_04703_amd.sim import derive
+    tile_used = derive(w, precision=abi.PIC_FP32_SPLIT, tile=tile)["tile"] if prec == abi.PIC_FP32_SPLIT else None
     wall, ms, launches, n_active, dlast = run(prec)
     steps = args.steps
     ps = n_active * steps / wall
@@ -135,7 +165,7 @@ def main():
                                "lab gamma 200) + cold plasma 1e16 cm^-3 at 2 ppc with immobile ions",
                    "particles_active": n_active, "cells": n_cells,
                    "precision": "fp32_split_fixed_point" if prec == abi.PIC_FP32_SPLIT else "fp64_plain",
-                   "kernel_variant": args.variant},
+                   "deposit_variant": args.variant, "tile": tile_used, "wg_per_cu": args.wg_per_cu},
         "fdtd_cell_updates_per_s": n_cells / (fdtd_ms * 1e-3) if fdtd_ms > 0 else None,
         "phase_ms_per_step": {"particles": part_ms, "fdtd": fdtd_ms, "window_ion_inject_sort": ms[2] / steps,
                               "step_events": ms[3] / steps},

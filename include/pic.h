@@ -119,14 +119,20 @@ typedef struct {
  * fixed_point_frac_bits: 0 = automatic from the peak current bound.
  * check_every: FP32 mode re-lays out its bins when needed, checked every this
  *              many steps (a host synchronisation); 0 = 64.
- * tile: cell tile of the FP32 binned kernels (each edge >= 4 and divides the grid,
- *       LDS of one workgroup <= 64 KiB); 0 = 8x8x4.
+ * tile: cell tile of the FP32 binned kernels, one of 8x8x4, 8x8x8, 8x8x16, 16x8x4,
+ *       16x16x4, 16x8x8 (edges divide the grid); 0,0,0 = the first of 16x8x8,
+ *       16x16x4, 8x8x16, 8x8x8, 16x8x4, 8x8x4 that divides the grid.
  * max_steps: sizing of the plasma capacity of the FP64 mode (injection between
  *            compactions, or over the whole run when record = 1).
  * record: 1 keeps particle slots stable (no compaction) so that
  *         pic_adjoint_step() can follow them; FP64 mode only.
- * variant: launch shape of the FP32 particle kernel: 0 = 512 threads per
- *          workgroup with 2 waves per SIMD, 1 = 384 threads with 3 waves per SIMD.
+ * variant: current deposition of the FP32 particle kernel: 0 = the Esirkepov
+ *          window pruned per wave of 64 particles (its last node along an axis
+ *          only when some particle of the wave crosses a half cell there),
+ *          1 = every contribution of a moving component, 2 = nonzero
+ *          contributions only, one branch each.  All give identical results.
+ * wg_per_cu: resident workgroups per compute unit of the FP32 particle kernel's
+ *            persistent grid; 0 = as many as registers and LDS allow.
  * stream: hipStream_t for all launches (NULL: null stream). */
 typedef struct {
     int32_t precision, pusher;
@@ -134,6 +140,7 @@ typedef struct {
     int32_t fixed_point_frac_bits, check_every;
     int32_t tile[3], max_steps;
     int32_t record, variant;
+    int32_t wg_per_cu, reserved;
     void *stream;
 } pic_options;
 
@@ -153,6 +160,7 @@ typedef struct {
     double dt, gamma_R, beta_R, u_R, n_ref_m3, w_beam, n0_norm, k_u_lab, B0_norm, k_bunch;
     double elongation, sigma_z_lab_cells, z_offset_cells;
     int32_t frac_bits, pusher;
+    int32_t tile[3], reserved;   /* FP32 mode: the cell tile in use */
 } pic_derived;
 PIC_API pic_status pic_derive(const pic_grid *g, const pic_frame *f, const pic_beam *b, const pic_plasma *p,
                       const pic_undulator *u, const pic_options *o, pic_derived *out);

@@ -50,7 +50,8 @@ class pic_undulator(C.Structure):
 class pic_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pusher", C.c_int32), ("fp64_gamma_threshold", C.c_double),
                 ("fixed_point_frac_bits", C.c_int32), ("check_every", C.c_int32), ("tile", C.c_int32 * 3),
-                ("max_steps", C.c_int32), ("record", C.c_int32), ("variant", C.c_int32), ("stream", C.c_void_p)]
+                ("max_steps", C.c_int32), ("record", C.c_int32), ("variant", C.c_int32),
+                ("wg_per_cu", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p)]
 
 
 class pic_layout(C.Structure):
@@ -61,7 +62,8 @@ class pic_layout(C.Structure):
 class pic_derived(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("dt", "gamma_R", "beta_R", "u_R", "n_ref_m3", "w_beam", "n0_norm",
                                           "k_u_lab", "B0_norm", "k_bunch", "elongation", "sigma_z_lab_cells",
-                                          "z_offset_cells")] + [("frac_bits", C.c_int32), ("pusher", C.c_int32)]
+                                          "z_offset_cells")] + [("frac_bits", C.c_int32), ("pusher", C.c_int32),
+                                                                ("tile", C.c_int32 * 3), ("reserved", C.c_int32)]
 
 
 class pic_diag_out(C.Structure):
@@ -133,7 +135,7 @@ class PicError(RuntimeError):
 
 def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHER_AUTO, record=0, max_steps=0,
                           check_every=0, tile=(0, 0, 0), frac_bits=0, gamma_threshold=0.0, stream=None,
-                          normals=None, variant=0):
+                          normals=None, variant=0, wg_per_cu=0):
     """Fill the C structs from a workload dictionary (plain field copies)."""
     g, fr, b, p, u = w["grid"], w["frame"], w["beam"], w["plasma"], w["undulator"]
     grid = pic_grid(g["nx"], g["ny"], g["nz"], 0, g["dx_m"], g["cfl"])
@@ -165,5 +167,6 @@ def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHE
     opt.max_steps = max_steps
     opt.record = record
     opt.variant = variant
+    opt.wg_per_cu = wg_per_cu
     opt.stream = stream
     return grid, frame, beam, plasma, und, opt

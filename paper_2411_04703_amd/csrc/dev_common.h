@@ -24,6 +24,8 @@ struct Params {
     int frac_bits, pad1;
     double fscale, finv;        // 2^frac_bits and its inverse
     int tx, ty, tz, ntx, nty, ntz, nbins, pad2;
+    // FP32 mode: packed cell = i | j << cbx | l << (cbx + cby); tile edges 2^lgx, 2^lgy, 2^lgz
+    int cbx, cby, lgx, lgy, lgz, pad3;
 };
 
 // Window position during one step (host-decided, deterministic from the step count).

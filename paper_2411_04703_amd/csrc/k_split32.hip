@@ -52,7 +52,8 @@ struct SplitState {
     int32_t *tmpcnt;       // 2 x nbins
     int64_t *tmpoff;       // 2 x (nbins + 2)
     int grid;              // persistent grid of the step kernel
-    int tpb;               // its workgroup size (launch shape variant)
+    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, const SpeciesIO *, FieldsT<float>,
+                 long long *, long long *, long long *, int32_t *);  // its instantiation (tile, deposit variant)
     int lds_bytes;
     SpeciesIO *ios;        // device descriptors: [cur 0][2], [cur 1][2], [flat init][2]
 };
@@ -139,8 +140,27 @@ __device__ inline void append(const OutStore &O, bool active, int bin, int cell,
 }
 
 __device__ inline int bin_of(const Params &P, int i, int j, int l) {
-    return i / P.tx + P.ntx * (j / P.ty + P.nty * (l / P.tz));
+    return (i >> P.lgx) + P.ntx * ((j >> P.lgy) + P.nty * (l >> P.lgz));
 }
+
+// packed particle cell: i | j << cbx | l << (cbx + cby) (shifts, no divisions)
+__device__ inline int pack_cell(const Params &P, int i, int j, int l) {
+    return i | (j << P.cbx) | (l << (P.cbx + P.cby));
+}
+__device__ inline void unpack_cell(const Params &P, int cell, int &i, int &j, int &l) {
+    i = cell & ((1 << P.cbx) - 1);
+    j = (cell >> P.cbx) & ((1 << P.cby) - 1);
+    l = cell >> (P.cbx + P.cby);
+}
+
+// periodic wrap of an index at most one period outside [0, n)
+__device__ inline int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// linear index of cell (i, j, ring plane p), i and j at most one period outside the grid
+__device__ inline int64_t near_cell(const Params &P, int i, int j, int p) {
+    return (int64_t)wrap1(i, P.nx) + (int64_t)P.nx * ((int64_t)wrap1(j, P.ny) + (int64_t)P.ny * p);
+}
+
 
 // number of valid particles of bin b in a store
 __device__ inline int bin_count(const int64_t *off, const int32_t *cnt, int b) {
@@ -149,14 +169,19 @@ __device__ inline int bin_count(const int64_t *off, const int32_t *cnt, int b) {
     return (int64_t)c < cap ? c : (int)cap;
 }
 
-// fixed-point value of one current contribution (round to nearest even)
-__device__ inline long long to_fixed(float v, double fscale, int32_t *flags) {
-    double s = (double)v * fscale;
-    if (!(fabs(s) <= 4.0e18)) {
-        atomicOr(flags, DFLAG_FIXED_OVERFLOW);
-        s = 0.0;
-    }
-    return (long long)rint(s);
+// fixed-point value of one current contribution, rounded to nearest even: adding
+// 1.5 * 2^52 leaves the integer rint(v 2^f) in the low mantissa bits whenever
+// |v 2^f| < 2^51, which fixed_ok() has established for the whole particle
+__device__ inline long long to_fixed(float v, double fscale) {
+    const double magic = 6755399441055744.0;  // 1.5 * 2^52
+    return __double_as_longlong(fma((double)v, fscale, magic)) - __double_as_longlong(magic);
+}
+
+// Every Esirkepov contribution of a particle is f P_c[m] A_c[a][b] with
+// |P_c| <= 1 and 0 <= A_c <= 9/16, so |f| bounds them all: one range check per
+// particle (false also for a non-finite f)
+__device__ inline bool fixed_ok(float f, double fscale) {
+    return fabs((double)f) * fscale < 2251799813685248.0;  // 2^51
 }
 
 // ---------------------------------------------------------------- particle math
@@ -166,10 +191,7 @@ struct PState {
 };
 
 __device__ inline void load_particle(const Part32 &in, int64_t s, const Params &P, PState &q) {
-    int cell = in.cell[s];
-    q.i = cell % P.nx;
-    q.j = (cell / P.nx) % P.ny;
-    q.l = cell / P.plane;
+    unpack_cell(P, in.cell[s], q.i, q.j, q.l);
     q.o[0] = in.ox[s];
     q.o[1] = in.oy[s];
     q.o[2] = in.oz[s];
@@ -221,61 +243,109 @@ __device__ inline bool push32(const Params &P, const float E[3], const float B[3
     return isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]);
 }
 
-// Esirkepov weights of a move X0 -> X1 (coordinates relative to the particle's cell)
+// Esirkepov weights of a move X0 -> X1 (coordinates relative to the particle's cell).
+// The four-node window along d starts one node below the lower of the nearest
+// nodes n0, n1 of X0, X1; its last node carries weight only when n0 != n1
+// (bit d of cross).
 struct Esk {
-    int base[3];
+    int base[3], cross;
     float S0[3][4], DS[3][4];
 };
 
 __device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
+    e.cross = 0;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        int n0 = X0[d] >= 0.5f ? 1 : 0;
-        int n1 = (int)floorf(X1[d] + 0.5f);
-        e.base[d] = (n0 < n1 ? n0 : n1) - 1;
-        for (int m = 0; m < 4; ++m) {
-            float node = (float)(e.base[d] + m);
-            e.S0[d][m] = spline2<float>(X0[d] - node);
-            e.DS[d][m] = spline2<float>(X1[d] - node) - e.S0[d][m];
-        }
+        const int n0 = X0[d] >= 0.5f ? 1 : 0;
+        const int n1 = (int)floorf(X1[d] + 0.5f);
+        const int lo = n0 < n1 ? n0 : n1;
+        e.base[d] = lo - 1;
+        e.cross |= n0 != n1 ? 1 << d : 0;
+        // the three nonzero weights around each nearest node, placed in the window
+        float w0[3], w1[3];
+        weights3<float>(X0[d] - (float)n0, w0);
+        weights3<float>(X1[d] - (float)n1, w1);
+        const bool h0 = n0 > lo, h1 = n1 > lo;  // window shifted by one node for this position
+        float S1[4];
+        e.S0[d][0] = h0 ? 0.0f : w0[0];
+        e.S0[d][1] = h0 ? w0[0] : w0[1];
+        e.S0[d][2] = h0 ? w0[1] : w0[2];
+        e.S0[d][3] = h0 ? w0[2] : 0.0f;
+        S1[0] = h1 ? 0.0f : w1[0];
+        S1[1] = h1 ? w1[0] : w1[1];
+        S1[2] = h1 ? w1[1] : w1[2];
+        S1[3] = h1 ? w1[2] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) e.DS[d][m] = S1[m] - e.S0[d][m];
     }
 }
 
-// every nonzero contribution: fn(c, r_along, r_a, r_b, value), r = node offsets
-// from the cell.  Per component c the Esirkepov current factorises:
+// Esirkepov contributions: fn(c, r_along, r_a, r_b, value), r = node offsets from
+// the particle's cell along c and along the other two axes a, b in cyclic order.
+// Per component c the current factorises:
 //   J_c(m, a, b) = f P_c[m] A_c[a][b],  P_c[m] = sum_{m' <= m} DS_c[m'],
-//   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3)
-// (a, b the other two axes in cyclic order).
-template <int C, typename F> __device__ inline void esk_component(const Esk &e, float f, F &&fn) {
+//   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3),
+// and P_c[2] = -DS_c[3] (the DS sum to zero), exactly zero without a crossing.
+// DEP 0 visits nonzero contributions only (one branch each); DEP 1 visits all
+// 48 of a component that moves along its axis; DEP 2 leaves out the window's
+// last node along an axis (m = 2, a = 3 or b = 3) when no lane of the wave
+// crosses there (wave-uniform branches).  The values visited differ only by
+// zeros, so the integer current sums are the same.
+template <int C, int DEP, typename F> __device__ inline void esk_component(const Esk &e, float f, F &&fn) {
     constexpr int CA = C == 2 ? 0 : C + 1, CB = C == 0 ? 2 : C - 1;
     float Pm[3];
     Pm[0] = e.DS[C][0];
     Pm[1] = Pm[0] + e.DS[C][1];
-    Pm[2] = Pm[1] + e.DS[C][2];
+    Pm[2] = -e.DS[C][3];
+    if (DEP != 0 && Pm[0] == 0.0f && Pm[1] == 0.0f && Pm[2] == 0.0f) return;
     float ub[4], vb[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         ub[b] = fmaf(0.5f, e.DS[CB][b], e.S0[CB][b]);
         vb[b] = fmaf(1.0f / 3.0f, e.DS[CB][b], 0.5f * e.S0[CB][b]);
     }
+    if (DEP == 2) {
+        const bool m2 = __any(e.cross & (1 << C)), a3 = __any(e.cross & (1 << CA)), b3 = __any(e.cross & (1 << CB));
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            if (mm == 1 && !m2) break;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                if (a == 3 && !a3) break;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (b == 3 && !b3) break;
+                    const float fa = f * fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
+                    if (mm == 0) {
+                        fn(C, e.base[C], e.base[CA] + a, e.base[CB] + b, fa * Pm[0]);
+                        fn(C, e.base[C] + 1, e.base[CA] + a, e.base[CB] + b, fa * Pm[1]);
+                    } else {
+                        fn(C, e.base[C] + 2, e.base[CA] + a, e.base[CB] + b, fa * Pm[2]);
+                    }
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             float A = fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
-            if (A == 0.0f) continue;
+            if (DEP == 0 && A == 0.0f) continue;
             float fa = f * A;
 #pragma unroll
             for (int m = 0; m < 3; ++m)
-                if (Pm[m] != 0.0f) fn(C, e.base[C] + m, e.base[CA] + a, e.base[CB] + b, fa * Pm[m]);
+                if (DEP != 0 || Pm[m] != 0.0f) fn(C, e.base[C] + m, e.base[CA] + a, e.base[CB] + b, fa * Pm[m]);
         }
 }
 
-template <typename F> __device__ inline void esk_visit(const Esk &e, float f, F &&fn) {
-    esk_component<0>(e, f, fn);
+template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, float f, F &&fn) {
+    esk_component<0, DEP>(e, f, fn);
     __builtin_amdgcn_sched_barrier(0);
-    esk_component<1>(e, f, fn);
+    esk_component<1, DEP>(e, f, fn);
     __builtin_amdgcn_sched_barrier(0);
-    esk_component<2>(e, f, fn);
+    esk_component<2, DEP>(e, f, fn);
 }
 
 // carry new offsets into the cell, apply the window shift; false if the particle left the band
@@ -313,11 +383,6 @@ __device__ inline bool renormalise(const Params &P, const StepCtx &S, PState &q)
 // out explicitly where wanted.
 
 // field value accessors: staged LDS box (tiled) or ring-buffered global arrays (untiled)
-struct LdsBox {
-    const float *F;   // 6 boxes of nE floats
-    int nE, ex, ey;   // box index of (half-)node index k (relative to t0) is k + 1
-    __device__ float at(int comp, int x, int y, int z) const { return F[comp * nE + (x + 1) + ex * ((y + 1) + ey * (z + 1))]; }
-};
 struct GlobalField {
     const Params *P;
     const float *const *F;  // E0 E1 E2 B0 B1 B2
@@ -393,13 +458,18 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
     Esk e;
     esk_setup(q.o, X1, e);
     long long *J[3] = {Jx, Jy, Jz};
-    esk_visit(e, q.w / (float)P.dt, [&](int c, int ra, int rb, int rc, float v) {
+    const float fq = q.w / (float)P.dt;
+    if (!fixed_ok(fq, P.fscale)) {
+        atomicOr(flags, DFLAG_FIXED_OVERFLOW);
+        return false;
+    }
+    esk_visit<0>(e, fq, [&](int c, int ra, int rb, int rc, float v) {
         int r[3];
         r[c] = ra;
         r[c == 2 ? 0 : c + 1] = rb;
         r[c == 0 ? 2 : c - 1] = rc;
         int p = ring_plane(q.l + r[2], S.k0r, P.nz);
-        long long iv = to_fixed(v, P.fscale, flags);
+        long long iv = to_fixed(v, P.fscale);
         atomicAdd((unsigned long long *)&J[c][cell_index(P, q.i + r[0], q.j + r[1], p)], (unsigned long long)iv);
     });
     for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
@@ -407,22 +477,40 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
 }
 
 // ---------------------------------------------------------------- the step kernel
-// TPB threads per workgroup, at least MINW waves per SIMD (register budget 512 / MINW)
-template <int TPB, int MINW>
-__global__ void __launch_bounds__(TPB, MINW) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
-                                                          int32_t *next, const SpeciesIO *ios, FieldsT<float> f,
-                                                          long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
+// Tile TX x TY x TZ cells (compile time, so that every LDS access of the gather
+// and the deposit is one per-particle base address plus an immediate offset),
+// ST threads, 2 waves per SIMD.  DEP selects the deposit variant (esk_component).
+template <int TX, int TY, int TZ> struct TileGeom {
+    static constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3, NE = EX * EY * EZ;  // E, B boxes (t0 - 1 ...)
+    // current boxes (origin t0 - 2): along their own axis TX + 4, across TX + 5
+    static constexpr int XX = TX + 4, XY = TY + 5, XZ = TZ + 5;
+    static constexpr int YX = TX + 5, YY = TY + 4, YZ = TZ + 5;
+    static constexpr int ZX = TX + 5, ZY = TY + 5, ZZ = TZ + 4;
+    static constexpr int NJX = XX * XY * XZ, NJY = YX * YY * YZ, NJZ = ZX * ZY * ZZ, NJ = NJX + NJY + NJZ;
+    static constexpr int NTAB = TZ + 3;
+    static constexpr int EBYTES = (6 * NE * 4 + 15) & ~15;
+    static constexpr int LDS = EBYTES + 8 * NJ + 16 * NTAB;
+};
+
+template <int EX, int EY, int NE> struct LdsBoxT {
+    const float *F;  // 6 boxes of NE floats; box index of (half-)node k (relative to t0) is k + 1
+    __device__ float at(int comp, int x, int y, int z) const {
+        return F[comp * NE + (x + 1) + EX * ((y + 1) + EY * (z + 1))];
+    }
+};
+
+template <int TX, int TY, int TZ, int DEP>
+__global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
+                                                      int32_t *next, const SpeciesIO *ios, FieldsT<float> f,
+                                                      long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
+    using G = TileGeom<TX, TY, TZ>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
     const int tid = threadIdx.x;
-    const int ex = P.tx + 3, ey = P.ty + 3, ez = P.tz + 3, nE = ex * ey * ez;
-    const int dJxx = P.tx + 4, dJxy = P.ty + 5, dJyx = P.tx + 5, dJyy = P.ty + 4, dJzx = P.tx + 5, dJzy = P.ty + 5;
-    const int nJx = dJxx * dJxy * (P.tz + 5), nJy = dJyx * dJyy * (P.tz + 5), nJz = dJzx * dJzy * (P.tz + 4);
-    const int nJ = nJx + nJy + nJz, nTab = P.tz + 3;
     float *Fs = (float *)smem;
-    long long *Js = (long long *)(smem + ((6 * nE * 4 + 15) & ~15));
-    double *tabA = (double *)(Js + nJ);
-    float *tabC = (float *)(tabA + nTab), *tabS = tabC + nTab;
+    long long *Js = (long long *)(smem + G::EBYTES);
+    double *tabA = (double *)(Js + G::NJ);
+    float *tabC = (float *)(tabA + G::NTAB), *tabS = tabC + G::NTAB;
     const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
     const int total = *nitems;
 
@@ -438,33 +526,32 @@ __global__ void __launch_bounds__(TPB, MINW) k_split_step(Params P, StepCtx S, c
 
         if (bin < 0) continue;  // overflow tails: k_split_overflow
 
-        const int t0x = (bin % P.ntx) * P.tx, t0y = ((bin / P.ntx) % P.nty) * P.ty,
-                  t0z = (bin / (P.ntx * P.nty)) * P.tz;
+        const int t0x = (bin % P.ntx) * TX, t0y = ((bin / P.ntx) % P.nty) * TY, t0z = (bin / (P.ntx * P.nty)) * TZ;
         // stage E, B: box node (a, b, c) <-> absolute node (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)
-        for (int k = tid; k < nE; k += TPB) {
-            int a = k % ex, b = (k / ex) % ey, c = k / (ex * ey);
+        for (int k = tid; k < G::NE; k += ST) {
+            const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
             int l = t0z - 1 + c;
             l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
-            int64_t o = cell_index(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+            const int64_t o = near_cell(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
-            for (int q = 0; q < 6; ++q) Fs[q * nE + k] = F6[q][o];
+            for (int q = 0; q < 6; ++q) Fs[q * G::NE + k] = F6[q][o];
         }
-        for (int k = tid; k < nJ; k += TPB) Js[k] = 0;
+        for (int k = tid; k < G::NJ; k += ST) Js[k] = 0;
         if (P.und_kind)
-            for (int k = tid; k < nTab; k += TPB) ext_plane(P, S.k0, t0z - 1 + k, S.t, tabA[k], tabC[k], tabS[k]);
+            for (int k = tid; k < G::NTAB; k += ST) ext_plane(P, S.k0, t0z - 1 + k, S.t, tabA[k], tabC[k], tabS[k]);
         __syncthreads();
 
-        const LdsBox box{Fs, nE, ex, ey};
+        const LdsBoxT<G::EX, G::EY, G::NE> box{Fs};
         const int64_t b0 = IO.in_off[bin];
         const int end = min(cnt, start + CH);
-        for (int base = start; base < end; base += TPB) {
+        for (int base = start; base < end; base += ST) {
             int k = base + tid;
             bool act = k < end;
             PState q;
             if (act) {
                 load_particle(IO.in, b0 + k, P, q);
                 const int li = q.i - t0x, lj = q.j - t0y, lk = q.l - t0z;
-                const bool inside = li >= 0 && li < P.tx && lj >= 0 && lj < P.ty && lk >= 0 && lk < P.tz &&
+                const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
                                     q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
                                     q.o[2] >= 0.0f && q.o[2] < 1.0f;
                 if (!inside) {
@@ -480,17 +567,21 @@ __global__ void __launch_bounds__(TPB, MINW) k_split_step(Params P, StepCtx S, c
                     } else {
                         Esk e;
                         esk_setup(q.o, X1, e);
-                        // LDS current boxes, origin t0 - 2: box index of offset r is lrel + r + 2
-                        esk_visit(e, q.w / (float)P.dt, [&](int c, int ra, int rb, int rc, float v) {
-                            long long iv = to_fixed(v, P.fscale, flags);
-                            int r[3];
-                            r[c] = ra;
-                            r[c == 2 ? 0 : c + 1] = rb;
-                            r[c == 0 ? 2 : c - 1] = rc;
-                            int x = li + r[0] + 2, y = lj + r[1] + 2, z = lk + r[2] + 2;
-                            int idx = c == 0   ? x + dJxx * (y + dJxy * z)
-                                      : c == 1 ? nJx + x + dJyx * (y + dJyy * z)
-                                               : nJx + nJy + x + dJzx * (y + dJzy * z);
+                        float fq = q.w / (float)P.dt;
+                        if (!fixed_ok(fq, P.fscale)) {
+                            atomicOr(flags, DFLAG_FIXED_OVERFLOW);
+                            fq = 0.0f;
+                        }
+                        // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2
+                        esk_visit<DEP>(e, fq, [&](int c, int ra, int rb, int rc, float v) {
+                            const long long iv = to_fixed(v, P.fscale);
+                            int idx;
+                            if (c == 0)  // (ra, rb, rc) = (x, y, z)
+                                idx = (li + ra + 2) + G::XX * ((lj + rb + 2) + G::XY * (lk + rc + 2));
+                            else if (c == 1)  // (y, z, x)
+                                idx = G::NJX + (li + rc + 2) + G::YX * ((lj + ra + 2) + G::YY * (lk + rb + 2));
+                            else  // (z, x, y)
+                                idx = G::NJX + G::NJY + (li + rb + 2) + G::ZX * ((lj + rc + 2) + G::ZY * (lk + ra + 2));
                             atomicAdd((unsigned long long *)&Js[idx], (unsigned long long)iv);
                         });
                         for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
@@ -498,40 +589,62 @@ __global__ void __launch_bounds__(TPB, MINW) k_split_step(Params P, StepCtx S, c
                     }
                 }
             }
-            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? q.i + P.nx * (q.j + P.ny * q.l) : 0, q.o,
+            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
                    q.u, q.w, flags);
         }
         __syncthreads();
         // flush nonzero LDS currents with global 64-bit integer atomics
-        for (int k = tid; k < nJ; k += TPB) {
-            long long v = Js[k];
+        for (int k = tid; k < G::NJ; k += ST) {
+            const long long v = Js[k];
             if (v == 0) continue;
-            int c, kk = k, dx, dy;
-            if (kk < nJx) {
-                c = 0;
-                dx = dJxx;
-                dy = dJxy;
-            } else if (kk < nJx + nJy) {
-                c = 1;
-                kk -= nJx;
-                dx = dJyx;
-                dy = dJyy;
+            int kk = k, x, y, z;
+            long long *J;
+            if (kk < G::NJX) {
+                const int yz = kk / G::XX;
+                x = kk - yz * G::XX;
+                z = yz / G::XY;
+                y = yz - z * G::XY;
+                J = Jx;
+            } else if (kk < G::NJX + G::NJY) {
+                kk -= G::NJX;
+                const int yz = kk / G::YX;
+                x = kk - yz * G::YX;
+                z = yz / G::YY;
+                y = yz - z * G::YY;
+                J = Jy;
             } else {
-                c = 2;
-                kk -= nJx + nJy;
-                dx = dJzx;
-                dy = dJzy;
+                kk -= G::NJX + G::NJY;
+                const int yz = kk / G::ZX;
+                x = kk - yz * G::ZX;
+                z = yz / G::ZY;
+                y = yz - z * G::ZY;
+                J = Jz;
             }
-            int x = kk % dx, y = (kk / dx) % dy, z = kk / (dx * dy);
-            int l = t0z - 2 + z;
+            const int l = t0z - 2 + z;
             if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
-            int64_t o = cell_index(P, t0x - 2 + x, t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
-            long long *J = c == 0 ? Jx : (c == 1 ? Jy : Jz);
+            const int64_t o = near_cell(P, t0x - 2 + x, t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
             atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
         }
         __syncthreads();
     }
 }
+
+// the tiles the step kernel is instantiated for
+#define PIC_SPLIT_TILES(X) X(8, 8, 4) X(8, 8, 8) X(8, 8, 16) X(16, 8, 4) X(16, 16, 4) X(16, 8, 8)
+
+using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, const SpeciesIO *,
+                            FieldsT<float>, long long *, long long *, long long *, int32_t *);
+
+static StepKernel step_kernel(int tx, int ty, int tz, int dep) {
+#define PIC_PICK(a, b, c)                                                                            \
+    if (tx == a && ty == b && tz == c)                                                               \
+        return dep == 0 ? k_split_step<a, b, c, 0> : (dep == 1 ? k_split_step<a, b, c, 1> : k_split_step<a, b, c, 2>);
+    PIC_SPLIT_TILES(PIC_PICK)
+#undef PIC_PICK
+    return nullptr;
+}
+
+bool split_tile_supported(int tx, int ty, int tz) { return step_kernel(tx, ty, tz, 0) != nullptr; }
 
 // overflow tails of the previous step: untiled path, one particle per thread,
 // persistent grid over the tail lengths read on the device
@@ -549,7 +662,7 @@ __global__ void __launch_bounds__(256) k_split_overflow(Params P, StepCtx S, con
                 load_particle(IO.in, IO.in_ovf_start + k, P, q);
                 act = particle_global(P, S, F6, Jx, Jy, Jz, q, flags);
             }
-            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? q.i + P.nx * (q.j + P.ny * q.l) : 0, q.o,
+            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
                    q.u, q.w, flags);
         }
     }
@@ -577,7 +690,7 @@ __global__ void __launch_bounds__(ST) k_rebin(Params P, const int4 *items, const
             bool act = k < end;
             PState q;
             if (act) load_particle(IO.in, b0 + k, P, q);
-            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? q.i + P.nx * (q.j + P.ny * q.l) : 0, q.o,
+            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
                    q.u, q.w, flags);
         }
     }
@@ -736,20 +849,20 @@ void split_setup(Ctx &c) {
     X->ios = (SpeciesIO *)(((uintptr_t)(X->tmpoff + nb + 8) + 15) & ~(uintptr_t)15);
     int eb;
     X->lds_bytes = lds_bytes_of(P, eb);
-    // launch shapes: 0 = 512 threads at 2 waves per SIMD (no spills), 1 = 384 threads at 3 waves per SIMD
-    X->tpb = c.opt.variant == 1 ? 384 : 512;
-    int waves = X->tpb / 64, max_wg_waves = c.opt.variant == 1 ? 12 : 8;
-    int per_cu = std::max(1, std::min(max_wg_waves / waves, (160 * 1024) / std::max(1, X->lds_bytes)));
+    // deposit: option 0 = wave-pruned windows, 1 = whole components, 2 = zero-skipping
+    X->kern = step_kernel(P.tx, P.ty, P.tz, c.opt.variant == 0 ? 2 : (c.opt.variant == 1 ? 1 : 0));
+    const void *kern = (const void *)X->kern;
+    (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, X->lds_bytes);
+    // persistent grid: resident workgroups per CU as registers and LDS allow, or as requested
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, ST, X->lds_bytes) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (c.opt.wg_per_cu > 0) per_cu = std::min(per_cu, c.opt.wg_per_cu);
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
     hipDeviceProp_t prop;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    int ncu = 256;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) ncu = prop.multiProcessorCount;
     X->grid = ncu * per_cu;
-    (void)hipFuncSetAttribute((const void *)k_split_step<512, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              X->lds_bytes);
-    (void)hipFuncSetAttribute((const void *)k_split_step<384, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              X->lds_bytes);
     (void)hipMemsetAsync(bins, 0, c.split_bins_bytes, c.st);
     // species descriptors (pointers only; their targets change, they do not)
     SpeciesIO h[6] = {species_io(c, 0, 0, X->s[0].bin_slots), species_io(c, 1, 0, X->s[1].bin_slots),
@@ -814,7 +927,7 @@ __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, d
     }
     int r = reserve_slot(act, 0, nflat);
     if (act) {
-        flat.cell[r] = s.i + P.nx * (s.j + P.ny * s.l);
+        flat.cell[r] = pack_cell(P, s.i, s.j, s.l);
         flat.ox[r] = s.o[0];
         flat.oy[r] = s.o[1];
         flat.oz[r] = s.o[2];
@@ -873,11 +986,11 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
         key = act ? bin_of(P, s.i, s.j, s.l) : 0;
     }
     if (bins) {
-        append(out, act, key, act ? s.i + P.nx * (s.j + P.ny * s.l) : 0, s.o, s.u, s.w, flags);
+        append(out, act, key, act ? pack_cell(P, s.i, s.j, s.l) : 0, s.o, s.u, s.w, flags);
     } else {
         int r = reserve_slot(act, 0, out.ovf);
         if (act) {
-            out.buf.cell[r] = s.i + P.nx * (s.j + P.ny * s.l);
+            out.buf.cell[r] = pack_cell(P, s.i, s.j, s.l);
             out.buf.ox[r] = s.o[0];
             out.buf.oy[r] = s.o[1];
             out.buf.oz[r] = s.o[2];
@@ -892,8 +1005,8 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
 __global__ void k_count_bins(Params P, Part32 flat, int64_t n, int32_t *cnt) {
     int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
     if (q >= n) return;
-    int cell = flat.cell[q];
-    int i = cell % P.nx, j = (cell / P.nx) % P.ny, l = cell / P.plane;
+    int i, j, l;
+    unpack_cell(P, flat.cell[q], i, j, l);
     atomicAdd(&cnt[bin_of(P, i, j, l)], 1);
 }
 
@@ -1024,12 +1137,8 @@ void split_step(Ctx &c, const StepCtx &S) {
     build_worklist(c, cur, 0, 0);  // overflow tails go to k_split_overflow
     timing_end(c, 2, t1);
     hipEvent_t t2 = timing_begin(c);
-    if (X.tpb == 384)
-        hipLaunchKernelGGL((k_split_step<384, 3>), dim3(X.grid), dim3(384), X.lds_bytes, c.st, P, S, X.items,
-                           X.nitems, X.next, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1], c.Ji[2], c.dflags);
-    else
-        hipLaunchKernelGGL((k_split_step<512, 2>), dim3(X.grid), dim3(512), X.lds_bytes, c.st, P, S, X.items,
-                           X.nitems, X.next, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1], c.Ji[2], c.dflags);
+    hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(ST), X.lds_bytes, c.st, P, S, X.items, X.nitems, X.next,
+                       X.ios + 2 * cur, f, c.Ji[0], c.Ji[1], c.Ji[2], c.dflags);
     hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1],
                        c.Ji[2], c.dflags);
     timing_end(c, 0, t2);
@@ -1160,8 +1269,8 @@ __global__ void k_split_out(Params P, int64_t k0, Part32 in, const int64_t *off,
             alive[d] = 1;
             continue;
         }
-        int cell = in.cell[s];
-        int i = cell % P.nx, j = (cell / P.nx) % P.ny, l = cell / P.plane;
+        int i, j, l;
+        unpack_cell(P, in.cell[s], i, j, l);
         double v[7] = {i + (double)in.ox[s], j + (double)in.oy[s], (double)(k0 + l) + (double)in.oz[s],
                        (double)in.ux[s], (double)in.uy[s], (double)in.uz[s], (double)in.w[s]};
         for (int q = 0; q < nout; ++q) dst[q * stride + d] = v[q];
@@ -1183,8 +1292,8 @@ __global__ void k_split_rho(Params P, int64_t k0, int k0r, Part32 in, const int6
     }
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
         int64_t s = s0 + k;
-        int cell = in.cell[s];
-        int i = cell % P.nx, j = (cell / P.nx) % P.ny, l = cell / P.plane;
+        int i, j, l;
+        unpack_cell(P, in.cell[s], i, j, l);
         float o[3] = {in.ox[s], in.oy[s], in.oz[s]};
         double w[3][3];
         int lo[3];

@@ -66,7 +66,8 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (o->precision != PIC_FP64_PLAIN && o->precision != PIC_FP32_SPLIT)
         return fail(err, PIC_EINVAL, "options: precision");
     if (o->pusher < -1 || o->pusher > 1) return fail(err, PIC_EINVAL, "options: pusher");
-    if (o->variant < 0 || o->variant > 1) return fail(err, PIC_EINVAL, "options: variant 0 or 1");
+    if (o->variant < 0 || o->variant > 2) return fail(err, PIC_EINVAL, "options: variant 0, 1 or 2");
+    if (o->wg_per_cu < 0 || o->wg_per_cu > 8) return fail(err, PIC_EINVAL, "options: wg_per_cu in [0, 8]");
     if (o->record && o->precision != PIC_FP64_PLAIN) return fail(err, PIC_EINVAL, "options: record needs FP64 mode");
 
     memset(&P, 0, sizeof P);
@@ -115,24 +116,50 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
                                              b->sigma_cells[2])
                                       : 0.0;
     double jb = 2.0 * P.gR * P.n0n + beam_peak + 1e-6;
+    // a single contribution is at most w / dt: FP32 mode converts it exactly while below 2^51
+    double vmax = 2.0 * std::max(P.wsheet, P.wbeam) / P.dt + 1e-6;
     int fb = o->fixed_point_frac_bits;
-    if (fb == 0) fb = 62 - (int)ceil(log2(64.0 * jb));
+    if (fb == 0) fb = std::min(62 - (int)ceil(log2(64.0 * jb)), 51 - (int)ceil(log2(vmax)));
     fb = std::min(56, std::max(20, fb));
     if (o->fixed_point_frac_bits > 60) return fail(err, PIC_ERANGE, "options: fixed_point_frac_bits > 60");
     P.frac_bits = fb;
     P.fscale = ldexp(1.0, fb);
     P.finv = ldexp(1.0, -fb);
     if (o->precision == PIC_FP32_SPLIT) {
-        int t[3] = {o->tile[0] ? o->tile[0] : 8, o->tile[1] ? o->tile[1] : 8, o->tile[2] ? o->tile[2] : 4};
+        int t[3] = {o->tile[0], o->tile[1], o->tile[2]};
+        if (!t[0] && !t[1] && !t[2]) {
+            // largest tile (least halo per cell) that divides the grid, by measured speed
+            static const int pref[6][3] = {{16, 8, 8}, {16, 16, 4}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4}};
+            for (int k = 0; k < 6; ++k)
+                if (g->nx % pref[k][0] == 0 && g->ny % pref[k][1] == 0 && g->nz % pref[k][2] == 0) {
+                    t[0] = pref[k][0];
+                    t[1] = pref[k][1];
+                    t[2] = pref[k][2];
+                    break;
+                }
+            if (!t[0]) return fail(err, PIC_EINVAL, "FP32 mode: grid edges must be multiples of 8, 8, 4");
+        }
         if (g->nx % t[0] || g->ny % t[1] || g->nz % t[2])
             return fail(err, PIC_EINVAL, "options: tile must divide the grid");
         if (t[0] < 4 || t[1] < 4 || t[2] < 4) return fail(err, PIC_EINVAL, "options: tile edges >= 4");
+        auto lg = [](int v) { int k = 0; while ((1 << k) < v) ++k; return k; };
+        for (int d3 = 0; d3 < 3; ++d3)
+            if (t[d3] != (1 << lg(t[d3]))) return fail(err, PIC_EINVAL, "options: tile edges must be powers of two");
+        P.cbx = lg(g->nx);
+        P.cby = lg(g->ny);
+        if (P.cbx + P.cby + lg(g->nz) > 31) return fail(err, PIC_EINVAL, "FP32 mode: grid needs more than 31 cell bits");
+        if (!split_tile_supported(t[0], t[1], t[2]))
+            return fail(err, PIC_EINVAL,
+                        "options: FP32 tile must be one of 8x8x4, 8x8x8, 8x8x16, 16x8x4, 16x16x4, 16x8x8");
+        P.lgx = lg(t[0]);
+        P.lgy = lg(t[1]);
+        P.lgz = lg(t[2]);
         // LDS of one workgroup: staged E, B (+halo) in FP32, int64 current boxes, field table
         int nE = (t[0] + 3) * (t[1] + 3) * (t[2] + 3);
         int nJ = (t[0] + 4) * (t[1] + 5) * (t[2] + 5) + (t[0] + 5) * (t[1] + 4) * (t[2] + 5) +
                  (t[0] + 5) * (t[1] + 5) * (t[2] + 4);
-        if (((6 * nE * 4 + 15) & ~15) + 8 * nJ + 16 * (t[2] + 3) > 64 * 1024)
-            return fail(err, PIC_EINVAL, "options: tile too large for 64 KiB of LDS");
+        if (((6 * nE * 4 + 15) & ~15) + 8 * nJ + 16 * (t[2] + 3) > 160 * 1024)
+            return fail(err, PIC_EINVAL, "options: tile too large for 160 KiB of LDS");
         P.tx = t[0];
         P.ty = t[1];
         P.tz = t[2];
@@ -156,6 +183,9 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     d.z_offset_cells = P.zoff;
     d.frac_bits = fb;
     d.pusher = P.pusher;
+    d.tile[0] = P.tx;
+    d.tile[1] = P.ty;
+    d.tile[2] = P.tz;
     return PIC_OK;
 }
 

@@ -117,6 +117,7 @@ int64_t compact64(Ctx &c, Part64 src, Part64 dst, int64_t n);  // returns surviv
 
 // FP32 split particles (k_split32.hip)
 void split_setup(Ctx &c);
+bool split_tile_supported(int tx, int ty, int tz);  // tiles the FP32 step kernel is built for
 void split_free(Ctx &c);
 void split_beam_init(Ctx &c, const double *normals_dev);
 pic_status split_plasma_fill(Ctx &c);  // also builds the initial bins of both species

@@ -39,7 +39,7 @@ def derive(w: dict, **opts) -> dict:
     out = abi.pic_derived()
     st = L.pic_derive(*[C.byref(x) for x in s], C.byref(out))
     _check(L, None, st, "pic_derive")
-    return {n: getattr(out, n) for n, _ in out._fields_}
+    return {n: (list(getattr(out, n)) if n == "tile" else getattr(out, n)) for n, _ in out._fields_}
 
 
 class Sim:

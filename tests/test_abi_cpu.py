@@ -100,6 +100,18 @@ def test_invalid_configurations_are_rejected(mutate, expect):
     assert e.value.status == expect
 
 
+@pytest.mark.parametrize("tile", [(4, 4, 4), (12, 8, 4), (8, 8, 32), (32, 32, 4)])
+def test_fp32_tiles_outside_the_built_set_are_rejected(tile):
+    with pytest.raises(abi.PicError) as e:
+        sim.query_layout(pin.workload(1), precision=abi.PIC_FP32_SPLIT, tile=tile)
+    assert e.value.status == abi.PIC_EINVAL
+
+
+@pytest.mark.parametrize("tile", [(8, 8, 4), (8, 8, 8), (8, 8, 16), (16, 8, 4), (16, 16, 4), (16, 8, 8)])
+def test_fp32_built_tiles_are_accepted(tile):
+    assert sim.query_layout(pin.workload(1), precision=abi.PIC_FP32_SPLIT, tile=tile).arena_bytes > 0
+
+
 def test_frac_bits_range_error():
     with pytest.raises(abi.PicError) as e:
         sim.query_layout(pin.workload(1), frac_bits=62)
