@@ -211,8 +211,11 @@ PIC_API pic_status pic_read(pic_ctx *c, int32_t which, void *dst, int64_t *count
 PIC_API pic_status pic_write(pic_ctx *c, int32_t which, const void *src, int64_t count);
 
 /* Checkpoint: copy the full dynamic state (particles, fields, window origin,
- * step counter, injection cursors) into / out of a DEVICE buffer of
- * layout.state_bytes.  Used for resume and by the adjoint's recomputation. */
+ * step counter, injection cursors; FP32 mode also its bin layout) into / out
+ * of a DEVICE buffer of layout.state_bytes, between steps.  A snapshot
+ * restores into any context of the same configuration and continues
+ * identically (bit for bit in FP32 mode).  Used for resume and by the
+ * adjoint's recomputation (FP64 mode). */
 PIC_API pic_status pic_get_state(pic_ctx *c, void *dst);
 PIC_API pic_status pic_set_state(pic_ctx *c, const void *src);
 

@@ -52,7 +52,7 @@ struct SplitState {
     int32_t *tmpcnt;       // 2 x nbins
     int64_t *tmpoff;       // 2 x (nbins + 2)
     int grid;              // persistent grid of the step kernel
-    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, const SpeciesIO *, FieldsT<float>,
+    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, SpeciesIO, SpeciesIO, FieldsT<float>,
                  long long *, long long *, long long *, int32_t *);  // its instantiation (tile, deposit variant)
     int lds_bytes;
     SpeciesIO *ios;        // device descriptors: [cur 0][2], [cur 1][2], [flat init][2]
@@ -410,17 +410,28 @@ template <class FA> __device__ inline void gather6(const FA &fa, const float o[3
                   sz = comp == 2 || comp == 3 || comp == 4;
         const float *wx = sx ? wH[0] : wI[0], *wy = sy ? wH[1] : wI[1], *wz = sz ? wH[2] : wI[2];
         const int bx = sx ? bH[0] : bI[0], by = sy ? bH[1] : bI[1], bz = sz ? bH[2] : bI[2];
+        // all 27 loads of the component first, so that one wait covers them
+        float v[27];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) v[(c * 3 + b) * 3 + a] = fa.at(comp, bx + a, by + b, bz + c);
         float acc = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                float r = fmaf(wx[2], fa.at(comp, bx + 2, by + b, bz + c),
-                               fmaf(wx[1], fa.at(comp, bx + 1, by + b, bz + c), wx[0] * fa.at(comp, bx, by + b, bz + c)));
+                const float *row = v + (c * 3 + b) * 3;
+                float r = fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0]));
                 acc = fmaf(wy[b] * wz[c], r, acc);
             }
         EB[comp] = acc;
-        __builtin_amdgcn_sched_barrier(0);  // keep the 27 loads of one component together (register pressure)
+        // loads of a component, then its arithmetic; components do not interleave (register pressure)
+        __builtin_amdgcn_sched_group_barrier(0x0100, 27, 0);
+        __builtin_amdgcn_sched_group_barrier(0x0002, 64, 0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -501,7 +512,7 @@ template <int EX, int EY, int NE> struct LdsBoxT {
 
 template <int TX, int TY, int TZ, int DEP>
 __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
-                                                      int32_t *next, const SpeciesIO *ios, FieldsT<float> f,
+                                                      int32_t *next, SpeciesIO io0, SpeciesIO io1, FieldsT<float> f,
                                                       long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
     using G = TileGeom<TX, TY, TZ>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -521,7 +532,8 @@ __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const
         __syncthreads();
         if (item >= total) break;
         const int4 it = items[item];
-        const SpeciesIO &IO = ios[it.x];
+        // descriptors by value (kernel arguments): their pointers are known to be global
+        const SpeciesIO &IO = it.x ? io1 : io0;
         const int bin = it.y, start = it.z, cnt = it.w;
 
         if (bin < 0) continue;  // overflow tails: k_split_overflow
@@ -632,7 +644,7 @@ __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const
 // the tiles the step kernel is instantiated for
 #define PIC_SPLIT_TILES(X) X(8, 8, 4) X(8, 8, 8) X(8, 8, 16) X(16, 8, 4) X(16, 16, 4) X(16, 8, 8)
 
-using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, const SpeciesIO *,
+using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, SpeciesIO, SpeciesIO,
                             FieldsT<float>, long long *, long long *, long long *, int32_t *);
 
 static StepKernel step_kernel(int tx, int ty, int tz, int dep) {
@@ -1138,7 +1150,8 @@ void split_step(Ctx &c, const StepCtx &S) {
     timing_end(c, 2, t1);
     hipEvent_t t2 = timing_begin(c);
     hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(ST), X.lds_bytes, c.st, P, S, X.items, X.nitems, X.next,
-                       X.ios + 2 * cur, f, c.Ji[0], c.Ji[1], c.Ji[2], c.dflags);
+                       species_io(c, 0, cur, X.s[0].bin_slots), species_io(c, 1, cur, X.s[1].bin_slots), f, c.Ji[0],
+                       c.Ji[1], c.Ji[2], c.dflags);
     hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1],
                        c.Ji[2], c.dflags);
     timing_end(c, 0, t2);
@@ -1170,6 +1183,37 @@ void split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n
                            c.dflags);
     }
     c.cur32 = o;
+}
+
+// ---------------------------------------------------------------- snapshots
+// FP32 state after a step: the fields (the current is zero between steps), the
+// bin layout and counts of both buffers, and the current particle buffer of
+// each species (the other buffer is rewritten by the next step).
+static uint64_t a256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes) {
+    return 6 * a256(4 * (uint64_t)nc) + a256(32 * (uint64_t)slots_b) + a256(32 * (uint64_t)slots_p) + a256(bins_bytes);
+}
+
+pic_status split_copy_state(Ctx &c, char *dev, bool save) {
+    SplitState &X = SS(c);
+    uint64_t o = 0;
+    auto mv = [&](void *mine, uint64_t bytes) -> pic_status {
+        PIC_HIP(c, hipMemcpyAsync(save ? dev + o : mine, save ? (const void *)mine : (const void *)(dev + o), bytes,
+                                  hipMemcpyDeviceToDevice, c.st));
+        o += a256(bytes);
+        return PIC_OK;
+    };
+    pic_status st;
+    for (int k = 0; k < 3; ++k)
+        if ((st = mv(c.E32[k], 4 * (uint64_t)c.P.nc)) != PIC_OK) return st;
+    for (int k = 0; k < 3; ++k)
+        if ((st = mv(c.B32[k], 4 * (uint64_t)c.P.nc)) != PIC_OK) return st;
+    for (int sp = 0; sp < 2; ++sp) {
+        Store &S = X.s[sp];
+        if ((st = mv(S.buf[c.cur32].cell, 32 * (uint64_t)(S.bin_slots + S.ovf_cap))) != PIC_OK) return st;
+    }
+    return mv(c.arena + c.split_off_bins, c.split_bins_bytes);
 }
 
 // periodic host check: re-lay out the bins when any overflowed or is nearly full

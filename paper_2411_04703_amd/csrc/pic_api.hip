@@ -263,8 +263,7 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
     if (o->precision == PIC_FP64_PLAIN)
         st += al256(60 * (uint64_t)std::max<int64_t>(pl.cap_b, 1)) + al256(60 * (uint64_t)std::max<int64_t>(pl.cap_p, 1));
     else
-        st += al256(32 * (uint64_t)(off[20] + pl.ovf_b)) + al256(32 * (uint64_t)(off[21] + pl.ovf_p)) +
-              al256(8 * (uint64_t)(P.nbins + 1) * 2 + 4 * (uint64_t)P.nbins * 4 + 64);
+        st = 256 + split_state_payload(P.nc, (int64_t)off[20] + pl.ovf_b, (int64_t)off[21] + pl.ovf_p, off[23]);
     pl.state = st;
     return PIC_OK;
 }
@@ -791,8 +790,8 @@ pic_status pic_get_state(pic_ctx *c, void *dst) {
         o += al256(bb);
         PIC_HIP(*c, hipMemcpyAsync(d + o, c->p64.x, pb, hipMemcpyDeviceToDevice, c->st));
     } else {
-        c->err = "pic_get_state: FP32 mode snapshots are not supported";
-        return PIC_EINVAL;
+        pic_status st = split_copy_state(*c, d + o, true);
+        if (st != PIC_OK) return st;
     }
     PIC_HIP(*c, hipStreamSynchronize(c->st));
     return PIC_OK;
@@ -818,8 +817,9 @@ pic_status pic_set_state(pic_ctx *c, const void *src) {
         o += al256(bb);
         PIC_HIP(*c, hipMemcpyAsync(c->p64.x, d + o, pb, hipMemcpyDeviceToDevice, c->st));
     } else {
-        c->err = "pic_set_state: FP32 mode snapshots are not supported";
-        return PIC_EINVAL;
+        c->cur32 = h.cur32;  // the snapshot's particles go to the buffer they came from
+        pic_status st = split_copy_state(*c, (char *)d + o, false);
+        if (st != PIC_OK) return st;
     }
     c->step = h.step;
     c->k0 = h.k0;

@@ -118,6 +118,8 @@ int64_t compact64(Ctx &c, Part64 src, Part64 dst, int64_t n);  // returns surviv
 // FP32 split particles (k_split32.hip)
 void split_setup(Ctx &c);
 bool split_tile_supported(int tx, int ty, int tz);  // tiles the FP32 step kernel is built for
+uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes);
+pic_status split_copy_state(Ctx &c, char *dev, bool save);  // snapshot <-> context (device buffer)
 void split_free(Ctx &c);
 void split_beam_init(Ctx &c, const double *normals_dev);
 pic_status split_plasma_fill(Ctx &c);  // also builds the initial bins of both species
