@@ -27,8 +27,9 @@
 
 namespace pic {
 
-constexpr int ST = 512;    // threads per workgroup
-constexpr int CH = 4096;   // particles per work item
+constexpr int ST = 512;    // threads per workgroup of the auxiliary kernels
+constexpr int SST = 768;   // threads per workgroup of the step kernel (3 waves per SIMD)
+constexpr int CH = 6 * SST;  // particles per work item
 constexpr int WT = 512;    // threads of the work-list kernels
 
 struct Store {
@@ -52,10 +53,13 @@ struct SplitState {
     int32_t *tmpcnt;       // 2 x nbins
     int64_t *tmpoff;       // 2 x (nbins + 2)
     int grid;              // persistent grid of the step kernel
-    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, SpeciesIO, SpeciesIO, FieldsT<float>,
-                 long long *, long long *, long long *, int32_t *);  // its instantiation (tile, deposit variant)
+    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, struct IOPair, FieldsT<float>,
+                 long long *, long long *, long long *, int32_t *, const double *, const float *,
+                 const float *);  // its instantiation (tile, deposit variant)
     int lds_bytes;
     SpeciesIO *ios;        // device descriptors: [cur 0][2], [cur 1][2], [flat init][2]
+    double *tabA;          // undulator phase table of the step, entry l + 1 for logical plane l (nz + 2)
+    float *tabC, *tabS;
 };
 
 static SplitState &SS(Ctx &c) { return *static_cast<SplitState *>(c.split); }
@@ -69,6 +73,13 @@ static int lds_bytes_of(const Params &P, int &ebytes) {
 }
 
 // ---------------------------------------------------------------- helpers
+// The particle and bin arrays are device (global) memory: accessed through
+// these casts the compiler uses global instructions with scalar bases even for
+// pointers it loaded from memory.
+template <typename T> __device__ inline __attribute__((address_space(1))) T *gbl(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Reserve one slot per active lane in bin `key` of cnt; lanes with equal keys
 // share one atomic.  Returns the rank within the bin (-1 for inactive lanes).
 // Called by every lane of the wave.
@@ -111,12 +122,17 @@ struct SpeciesIO {
     OutStore out;
 };
 
+// both species' descriptors as one kernel argument
+struct IOPair {
+    SpeciesIO s[2];
+};
+
 // append (active lanes) to bin `bin` of the output store; overflow tail when the bin is full
 __device__ inline void append(const OutStore &O, bool active, int bin, int cell, const float o[3], const float u[3],
                               float w, int32_t *flags) {
     int r = reserve_slot(active, active ? bin : 0, O.cnt);
     if (!active) return;
-    int64_t b0 = O.off[bin], cap = O.off[bin + 1] - b0;
+    int64_t b0 = gbl(O.off)[bin], cap = gbl(O.off)[bin + 1] - b0;
     int64_t s;
     if (r < cap) {
         s = b0 + r;
@@ -128,15 +144,15 @@ __device__ inline void append(const OutStore &O, bool active, int bin, int cell,
         }
         s = O.bin_slots + k;
     }
-    Part32 b = O.buf;
-    b.cell[s] = cell;
-    b.ox[s] = o[0];
-    b.oy[s] = o[1];
-    b.oz[s] = o[2];
-    b.ux[s] = u[0];
-    b.uy[s] = u[1];
-    b.uz[s] = u[2];
-    b.w[s] = w;
+    const Part32 &b = O.buf;
+    gbl(b.cell)[s] = cell;
+    gbl(b.ox)[s] = o[0];
+    gbl(b.oy)[s] = o[1];
+    gbl(b.oz)[s] = o[2];
+    gbl(b.ux)[s] = u[0];
+    gbl(b.uy)[s] = u[1];
+    gbl(b.uz)[s] = u[2];
+    gbl(b.w)[s] = w;
 }
 
 __device__ inline int bin_of(const Params &P, int i, int j, int l) {
@@ -191,14 +207,14 @@ struct PState {
 };
 
 __device__ inline void load_particle(const Part32 &in, int64_t s, const Params &P, PState &q) {
-    unpack_cell(P, in.cell[s], q.i, q.j, q.l);
-    q.o[0] = in.ox[s];
-    q.o[1] = in.oy[s];
-    q.o[2] = in.oz[s];
-    q.u[0] = in.ux[s];
-    q.u[1] = in.uy[s];
-    q.u[2] = in.uz[s];
-    q.w = in.w[s];
+    unpack_cell(P, gbl(in.cell)[s], q.i, q.j, q.l);
+    q.o[0] = gbl(in.ox)[s];
+    q.o[1] = gbl(in.oy)[s];
+    q.o[2] = gbl(in.oz)[s];
+    q.u[0] = gbl(in.ux)[s];
+    q.u[1] = gbl(in.uy)[s];
+    q.u[2] = gbl(in.uz)[s];
+    q.w = gbl(in.w)[s];
 }
 
 // undulator field at logical plane l: the plane's phase and envelope argument in
@@ -209,6 +225,12 @@ __device__ inline void ext_plane(const Params &P, int64_t k0, int l, double t, d
     sincos(P.ku * a_l, &sn, &cs);
     c = (float)cs;
     s = (float)sn;
+}
+
+// per step: ext_plane of every logical plane -1 .. nz (entry l + 1)
+__global__ void k_ext_table(Params P, StepCtx S, double *tabA, float *tabC, float *tabS) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < P.nz + 2) ext_plane(P, S.k0, e - 1, S.t, tabA[e], tabC[e], tabS[e]);
 }
 
 __device__ inline void ext32(const Params &P, double a_l, float cphi, float sphi, float oz, float E[3], float B[3]) {
@@ -410,28 +432,24 @@ template <class FA> __device__ inline void gather6(const FA &fa, const float o[3
                   sz = comp == 2 || comp == 3 || comp == 4;
         const float *wx = sx ? wH[0] : wI[0], *wy = sy ? wH[1] : wI[1], *wz = sz ? wH[2] : wI[2];
         const int bx = sx ? bH[0] : bI[0], by = sy ? bH[1] : bI[1], bz = sz ? bH[2] : bI[2];
-        // all 27 loads of the component first, so that one wait covers them
-        float v[27];
+        float acc = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) {
+            // the 9 loads of a plane first, so that one wait covers them
+            float v[9];
 #pragma unroll
             for (int b = 0; b < 3; ++b)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) v[(c * 3 + b) * 3 + a] = fa.at(comp, bx + a, by + b, bz + c);
-        float acc = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
+                for (int a = 0; a < 3; ++a) v[b * 3 + a] = fa.at(comp, bx + a, by + b, bz + c);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const float *row = v + (c * 3 + b) * 3;
+                const float *row = v + b * 3;
                 float r = fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0]));
                 acc = fmaf(wy[b] * wz[c], r, acc);
             }
+        }
         EB[comp] = acc;
-        // loads of a component, then its arithmetic; components do not interleave (register pressure)
-        __builtin_amdgcn_sched_group_barrier(0x0100, 27, 0);
-        __builtin_amdgcn_sched_group_barrier(0x0002, 64, 0);
-        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);  // components do not interleave (register pressure)
     }
 }
 
@@ -511,9 +529,10 @@ template <int EX, int EY, int NE> struct LdsBoxT {
 };
 
 template <int TX, int TY, int TZ, int DEP>
-__global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
-                                                      int32_t *next, SpeciesIO io0, SpeciesIO io1, FieldsT<float> f,
-                                                      long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
+__global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
+                                                      int32_t *next, IOPair iop, FieldsT<float> f,
+                                                      long long *Jx, long long *Jy, long long *Jz, int32_t *flags,
+                                                      const double *gtabA, const float *gtabC, const float *gtabS) {
     using G = TileGeom<TX, TY, TZ>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
@@ -528,19 +547,23 @@ __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const
     for (;;) {
         if (tid == 0) s_item = atomicAdd(next, 1);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads of the item and its descriptor
         __syncthreads();
         if (item >= total) break;
         const int4 it = items[item];
-        // descriptors by value (kernel arguments): their pointers are known to be global
-        const SpeciesIO &IO = it.x ? io1 : io0;
-        const int bin = it.y, start = it.z, cnt = it.w;
+        const int sp = __builtin_amdgcn_readfirstlane(it.x), bin = __builtin_amdgcn_readfirstlane(it.y),
+                  start = __builtin_amdgcn_readfirstlane(it.z), cnt = __builtin_amdgcn_readfirstlane(it.w);
+        // descriptors by value (kernel arguments): their pointers are known to be global, and
+        // indexing with the uniform species loads just this item's descriptor with scalar loads
+        const SpeciesIO &IO = iop.s[sp];
 
         if (bin < 0) continue;  // overflow tails: k_split_overflow
 
         const int t0x = (bin % P.ntx) * TX, t0y = ((bin / P.ntx) % P.nty) * TY, t0z = (bin / (P.ntx * P.nty)) * TZ;
+        const int64_t b0 = gbl(IO.in_off)[bin];
+        const int end = min(cnt, start + CH);
         // stage E, B: box node (a, b, c) <-> absolute node (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)
-        for (int k = tid; k < G::NE; k += ST) {
+        for (int k = tid; k < G::NE; k += SST) {
             const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
             int l = t0z - 1 + c;
             l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
@@ -548,20 +571,21 @@ __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const
 #pragma unroll
             for (int q = 0; q < 6; ++q) Fs[q * G::NE + k] = F6[q][o];
         }
-        for (int k = tid; k < G::NJ; k += ST) Js[k] = 0;
+        for (int k = tid; k < G::NJ; k += SST) Js[k] = 0;
         if (P.und_kind)
-            for (int k = tid; k < G::NTAB; k += ST) ext_plane(P, S.k0, t0z - 1 + k, S.t, tabA[k], tabC[k], tabS[k]);
+            for (int k = tid; k < G::NTAB; k += SST) {  // planes t0z - 1 ...: table entries t0z ...
+                tabA[k] = gtabA[t0z + k];
+                tabC[k] = gtabC[t0z + k];
+                tabS[k] = gtabS[t0z + k];
+            }
         __syncthreads();
 
         const LdsBoxT<G::EX, G::EY, G::NE> box{Fs};
-        const int64_t b0 = IO.in_off[bin];
-        const int end = min(cnt, start + CH);
-        for (int base = start; base < end; base += ST) {
-            int k = base + tid;
-            bool act = k < end;
+        for (int base = start; base < end; base += SST) {
+            bool act = base + tid < end;
             PState q;
             if (act) {
-                load_particle(IO.in, b0 + k, P, q);
+                load_particle(IO.in, b0 + base + tid, P, q);
                 const int li = q.i - t0x, lj = q.j - t0y, lk = q.l - t0z;
                 const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
                                     q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
@@ -606,7 +630,7 @@ __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const
         }
         __syncthreads();
         // flush nonzero LDS currents with global 64-bit integer atomics
-        for (int k = tid; k < G::NJ; k += ST) {
+        for (int k = tid; k < G::NJ; k += SST) {
             const long long v = Js[k];
             if (v == 0) continue;
             int kk = k, x, y, z;
@@ -644,8 +668,9 @@ __global__ void __launch_bounds__(ST, 2) k_split_step(Params P, StepCtx S, const
 // the tiles the step kernel is instantiated for
 #define PIC_SPLIT_TILES(X) X(8, 8, 4) X(8, 8, 8) X(8, 8, 16) X(16, 8, 4) X(16, 16, 4) X(16, 8, 8)
 
-using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, SpeciesIO, SpeciesIO,
-                            FieldsT<float>, long long *, long long *, long long *, int32_t *);
+using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, IOPair,
+                            FieldsT<float>, long long *, long long *, long long *, int32_t *, const double *,
+                            const float *, const float *);
 
 static StepKernel step_kernel(int tx, int ty, int tz, int dep) {
 #define PIC_PICK(a, b, c)                                                                            \
@@ -859,6 +884,9 @@ void split_setup(Ctx &c) {
     X->tmpcnt = (int32_t *)(X->scan_part + nblocks(2 * nb, WT) + 8);
     X->tmpoff = (int64_t *)(X->tmpcnt + 2 * nb + 8);
     X->ios = (SpeciesIO *)(((uintptr_t)(X->tmpoff + nb + 8) + 15) & ~(uintptr_t)15);
+    X->tabA = (double *)(((uintptr_t)(X->ios + 6) + 15) & ~(uintptr_t)15);
+    X->tabC = (float *)(X->tabA + P.nz + 2);
+    X->tabS = X->tabC + P.nz + 2;
     int eb;
     X->lds_bytes = lds_bytes_of(P, eb);
     // deposit: option 0 = wave-pruned windows, 1 = whole components, 2 = zero-skipping
@@ -867,7 +895,7 @@ void split_setup(Ctx &c) {
     (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, X->lds_bytes);
     // persistent grid: resident workgroups per CU as registers and LDS allow, or as requested
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, ST, X->lds_bytes) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, SST, X->lds_bytes) != hipSuccess || per_cu < 1)
         per_cu = 1;
     if (c.opt.wg_per_cu > 0) per_cu = std::min(per_cu, c.opt.wg_per_cu);
     int dev = 0, ncu = 256;
@@ -1147,11 +1175,14 @@ void split_step(Ctx &c, const StepCtx &S) {
     timing_end(c, 1, t0);
     hipEvent_t t1 = timing_begin(c);
     build_worklist(c, cur, 0, 0);  // overflow tails go to k_split_overflow
+    if (P.und_kind)
+        hipLaunchKernelGGL(k_ext_table, dim3(nblocks(P.nz + 2, 256)), dim3(256), 0, c.st, P, S, X.tabA, X.tabC,
+                           X.tabS);
     timing_end(c, 2, t1);
     hipEvent_t t2 = timing_begin(c);
-    hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(ST), X.lds_bytes, c.st, P, S, X.items, X.nitems, X.next,
-                       species_io(c, 0, cur, X.s[0].bin_slots), species_io(c, 1, cur, X.s[1].bin_slots), f, c.Ji[0],
-                       c.Ji[1], c.Ji[2], c.dflags);
+    hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(SST), X.lds_bytes, c.st, P, S, X.items, X.nitems, X.next,
+                       IOPair{{species_io(c, 0, cur, X.s[0].bin_slots), species_io(c, 1, cur, X.s[1].bin_slots)}}, f,
+                       c.Ji[0], c.Ji[1], c.Ji[2], c.dflags, X.tabA, X.tabC, X.tabS);
     hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1],
                        c.Ji[2], c.dflags);
     timing_end(c, 0, t2);

@@ -129,7 +129,7 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
         int t[3] = {o->tile[0], o->tile[1], o->tile[2]};
         if (!t[0] && !t[1] && !t[2]) {
             // largest tile (least halo per cell) that divides the grid, by measured speed
-            static const int pref[6][3] = {{16, 8, 8}, {16, 16, 4}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4}};
+            static const int pref[6][3] = {{16, 16, 4}, {16, 8, 8}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4}};
             for (int k = 0; k < 6; ++k)
                 if (g->nx % pref[k][0] == 0 && g->ny % pref[k][1] == 0 && g->nz % pref[k][2] == 0) {
                     t[0] = pref[k][0];
@@ -241,7 +241,7 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
         uint64_t bins_bytes = 8 * (uint64_t)(nbins + 1) * 4 + 4 * (uint64_t)nbins * 4 + 256;
         off[13] = take(bins_bytes);
         int64_t items_cap = (cb + cp + pl.ovf_b + pl.ovf_p) / 4096 + 2 * nbins + 64;
-        uint64_t wl_bytes = 16 * (uint64_t)items_cap + 8 * (uint64_t)((2 * nbins) / 512 + 16) +
+        uint64_t wl_bytes = 16 * (uint64_t)(P.nz + 8) + 16 * (uint64_t)items_cap + 8 * (uint64_t)((2 * nbins) / 512 + 16) +
                             4 * (uint64_t)(2 * nbins + 8) + 8 * (uint64_t)(nbins + 8) + 4096;
         off[14] = take(wl_bytes);
         off[20] = cb;  // slot capacities (not offsets)
