@@ -34,6 +34,28 @@ def algorithmic_bytes(precision: int, n_particles: float, n_cells: int) -> dict:
     return {"per_particle": per_p, "per_cell": per_c, "total": per_p * n_particles + per_c * n_cells}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_split_step_128x128x512_hbm_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2411_04703_amd", "csrc", "k_split32.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the particle kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (calibrated against a plain copy), or None when the
+    kernel source changed since they were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+    if len(vals) != 2:
+        return None
+    if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != vals["kernel_source_sha256"].strip():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(seconds_budget: float = 20.0) -> dict:
     """The oracle, single-threaded FP64, on 1/64 of the workload's volume (same densities)."""
     import numpy as np  # noqa: F401
@@ -170,7 +192,9 @@ def main():
         "phase_ms_per_step": {"particles": part_ms, "fdtd": fdtd_ms, "window_ion_inject_sort": ms[2] / steps,
                               "step_events": ms[3] / steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (prec == abi.PIC_FP32_SPLIT and tile == (0, 0, 0)
+                                                       and args.variant == 0) else None,
                      "kernel": "fused particle kernel(s): gather, push, deposit",
                      "bytes_per_step": ab["total"], "bytes_per_particle": ab["per_particle"],
                      "bytes_per_cell": ab["per_cell"], "avg_ms_per_step": part_ms,
