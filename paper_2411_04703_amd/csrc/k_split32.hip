@@ -53,13 +53,15 @@ struct SplitState {
     int32_t *tmpcnt;       // 2 x nbins
     int64_t *tmpoff;       // 2 x (nbins + 2)
     int grid;              // persistent grid of the step kernel
-    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, struct IOPair, FieldsT<float>,
+    void (*kern)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, int, struct IOPair, FieldsT<float>,
                  long long *, long long *, long long *, int32_t *, const double *, const float *,
                  const float *);  // its instantiation (tile, deposit variant)
     int lds_bytes;
     SpeciesIO *ios;        // device descriptors: [cur 0][2], [cur 1][2], [flat init][2]
     double *tabA;          // undulator phase table of the step, entry l + 1 for logical plane l (nz + 2)
     float *tabC, *tabS;
+    int nslab;             // work queues: slabs of whole bin layers (one per XCD when they divide evenly)
+    int32_t *qnext, *qstart;  // per-slab item counters; slab q's items are [qstart[q], qstart[q + 1])
 };
 
 static SplitState &SS(Ctx &c) { return *static_cast<SplitState *>(c.split); }
@@ -529,8 +531,8 @@ template <int EX, int EY, int NE> struct LdsBoxT {
 };
 
 template <int TX, int TY, int TZ, int DEP>
-__global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *nitems,
-                                                      int32_t *next, IOPair iop, FieldsT<float> f,
+__global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *qstart,
+                                                      int32_t *qnext, int nslab, IOPair iop, FieldsT<float> f,
                                                       long long *Jx, long long *Jy, long long *Jz, int32_t *flags,
                                                       const double *gtabA, const float *gtabC, const float *gtabS) {
     using G = TileGeom<TX, TY, TZ>;
@@ -542,14 +544,27 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
     double *tabA = (double *)(Js + G::NJ);
     float *tabC = (float *)(tabA + G::NTAB), *tabS = tabC + G::NTAB;
     const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
-    const int total = *nitems;
+    // slab queue of this workgroup's XCD first, then the others' (work stealing)
+    int q = (int)(blockIdx.x % (unsigned)nslab), hops = 0;
 
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(next, 1);
+        if (tid == 0) {
+            int it = -1;
+            while (hops < nslab) {
+                const int k = qstart[q] + atomicAdd(&qnext[q], 1);
+                if (k < qstart[q + 1]) {
+                    it = k;
+                    break;
+                }
+                q = q + 1 == nslab ? 0 : q + 1;
+                ++hops;
+            }
+            s_item = it;
+        }
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads of the item and its descriptor
         __syncthreads();
-        if (item >= total) break;
+        if (item < 0) break;
         const int4 it = items[item];
         const int sp = __builtin_amdgcn_readfirstlane(it.x), bin = __builtin_amdgcn_readfirstlane(it.y),
                   start = __builtin_amdgcn_readfirstlane(it.z), cnt = __builtin_amdgcn_readfirstlane(it.w);
@@ -668,7 +683,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
 // the tiles the step kernel is instantiated for
 #define PIC_SPLIT_TILES(X) X(8, 8, 4) X(8, 8, 8) X(8, 8, 16) X(16, 8, 4) X(16, 16, 4) X(16, 8, 8)
 
-using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, IOPair,
+using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, int, IOPair,
                             FieldsT<float>, long long *, long long *, long long *, int32_t *, const double *,
                             const float *, const float *);
 
@@ -740,13 +755,25 @@ __global__ void __launch_bounds__(ST) k_rebin(Params P, const int4 *items, const
 // totals, per-block writes.  They also clear the output counters.
 __device__ inline int items_of(int n) { return (n + CH - 1) / CH; }
 
+// Work-list entry e (0 <= e < 2 nbins) in slab-major order: the bins form
+// nslab slabs of whole z layers (bins are numbered z-major), and within a slab
+// the beam's bins come before the plasma's.
+__device__ inline void entry_of(int e, int nbins, int nslab, int &sp, int &bin) {
+    const int bps = nbins / nslab, s = e / (2 * bps), r = e - s * 2 * bps;
+    sp = r >= bps ? 1 : 0;
+    bin = s * bps + (r - sp * bps);
+}
+
 __global__ void k_wl_count(const int64_t *off0, const int32_t *cnt0, const int64_t *off1, const int32_t *cnt1,
-                           int nbins, int64_t *part) {
+                           int nbins, int nslab, int64_t *part) {
     __shared__ int64_t s[WT];
     int e = blockIdx.x * WT + threadIdx.x;
     int v = 0;
-    if (e < nbins) v = items_of(bin_count(off0, cnt0, e));
-    else if (e < 2 * nbins) v = items_of(bin_count(off1, cnt1, e - nbins));
+    if (e < 2 * nbins) {
+        int sp, bin;
+        entry_of(e, nbins, nslab, sp, bin);
+        v = items_of(sp ? bin_count(off1, cnt1, bin) : bin_count(off0, cnt0, bin));
+    }
     s[threadIdx.x] = v;
     __syncthreads();
     for (int h = WT / 2; h > 0; h >>= 1) {
@@ -758,7 +785,7 @@ __global__ void k_wl_count(const int64_t *off0, const int32_t *cnt0, const int64
 
 __global__ void k_wl_scan(int64_t *part, int nblk, const int32_t *ovf0, int64_t ocap0, const int32_t *ovf1,
                           int64_t ocap1, int32_t *nitems, int32_t *next, int4 *items, int64_t items_cap,
-                          int32_t *clr0, int32_t *clr1) {
+                          int32_t *clr0, int32_t *clr1, int32_t *qnext, int32_t *qstart, int nslab) {
     if (threadIdx.x != 0) return;
     int64_t acc = 0;
     for (int b = 0; b < nblk; ++b) {
@@ -766,6 +793,8 @@ __global__ void k_wl_scan(int64_t *part, int nblk, const int32_t *ovf0, int64_t 
         part[b] = acc;
         acc += v;
     }
+    for (int q = 0; q < nslab; ++q) qnext[q] = 0;
+    qstart[nslab] = (int32_t)min(acc, items_cap);  // the slab queues end before the overflow items
     int o0 = (int)min((int64_t)*ovf0, ocap0), o1 = (int)min((int64_t)*ovf1, ocap1);
     for (int k = 0; k < items_of(o0) && acc < items_cap; ++k) items[acc++] = make_int4(0, -1, k * CH, o0);
     for (int k = 0; k < items_of(o1) && acc < items_cap; ++k) items[acc++] = make_int4(1, -1, k * CH, o1);
@@ -776,13 +805,15 @@ __global__ void k_wl_scan(int64_t *part, int nblk, const int32_t *ovf0, int64_t 
 }
 
 __global__ void k_wl_write(const int64_t *off0, const int32_t *cnt0, const int64_t *off1, const int32_t *cnt1,
-                           int nbins, const int64_t *part, int4 *items, int64_t items_cap, int32_t *zero0,
-                           int32_t *zero1) {
+                           int nbins, int nslab, const int64_t *part, int4 *items, int64_t items_cap, int32_t *zero0,
+                           int32_t *zero1, int32_t *qstart) {
     __shared__ int64_t s[WT];
     int e = blockIdx.x * WT + threadIdx.x;
-    int v = 0, c = 0;
-    if (e < nbins) c = bin_count(off0, cnt0, e);
-    else if (e < 2 * nbins) c = bin_count(off1, cnt1, e - nbins);
+    int v = 0, c = 0, sp = 0, bin = 0;
+    if (e < 2 * nbins) {
+        entry_of(e, nbins, nslab, sp, bin);
+        c = sp ? bin_count(off1, cnt1, bin) : bin_count(off0, cnt0, bin);
+    }
     v = items_of(c);
     s[threadIdx.x] = v;
     __syncthreads();
@@ -793,11 +824,14 @@ __global__ void k_wl_write(const int64_t *off0, const int32_t *cnt0, const int64
         __syncthreads();
     }
     int64_t o = part[blockIdx.x] + s[threadIdx.x] - v;
-    int sp = e < nbins ? 0 : 1, bin = e < nbins ? e : e - nbins;
     for (int k = 0; k < v; ++k)
         if (o + k < items_cap) items[o + k] = make_int4(sp, bin, k * CH, c);
-    if (e < nbins) zero0[e] = 0;
-    else if (e < 2 * nbins) zero1[e - nbins] = 0;
+    if (e < 2 * nbins) {
+        if (sp) zero1[bin] = 0;
+        else zero0[bin] = 0;
+        const int bps = nbins / nslab;
+        if (e % (2 * bps) == 0) qstart[e / (2 * bps)] = (int32_t)min(o, items_cap);  // first entry of a slab
+    }
 }
 
 // in_cap0/1: how many overflow-tail particles the input buffer can hold
@@ -808,11 +842,11 @@ static void build_worklist(Ctx &c, int cur, int64_t in_cap0, int64_t in_cap1) {
     int o = cur ^ 1;
     Store &b = X.s[0], &p = X.s[1];
     hipLaunchKernelGGL(k_wl_count, dim3(nblk), dim3(WT), 0, c.st, b.off[cur], b.cnt[cur], p.off[cur], p.cnt[cur], nb,
-                       X.scan_part);
+                       X.nslab, X.scan_part);
     hipLaunchKernelGGL(k_wl_scan, dim3(1), dim3(64), 0, c.st, X.scan_part, nblk, b.ovf[cur], in_cap0, p.ovf[cur],
-                       in_cap1, X.nitems, X.next, X.items, X.items_cap, b.ovf[o], p.ovf[o]);
+                       in_cap1, X.nitems, X.next, X.items, X.items_cap, b.ovf[o], p.ovf[o], X.qnext, X.qstart, X.nslab);
     hipLaunchKernelGGL(k_wl_write, dim3(nblk), dim3(WT), 0, c.st, b.off[cur], b.cnt[cur], p.off[cur], p.cnt[cur], nb,
-                       X.scan_part, X.items, X.items_cap, b.cnt[o], p.cnt[o]);
+                       X.nslab, X.scan_part, X.items, X.items_cap, b.cnt[o], p.cnt[o], X.qstart);
 }
 
 static SpeciesIO species_io(Ctx &c, int sp, int cur, int64_t in_ovf_start) {
@@ -887,6 +921,9 @@ void split_setup(Ctx &c) {
     X->tabA = (double *)(((uintptr_t)(X->ios + 6) + 15) & ~(uintptr_t)15);
     X->tabC = (float *)(X->tabA + P.nz + 2);
     X->tabS = X->tabC + P.nz + 2;
+    X->qnext = (int32_t *)(((uintptr_t)(X->tabS + P.nz + 2) + 15) & ~(uintptr_t)15);
+    X->qstart = X->qnext + 16;
+    X->nslab = P.ntz % 8 == 0 ? 8 : 1;  // workgroups are dispatched round-robin over the 8 XCDs
     int eb;
     X->lds_bytes = lds_bytes_of(P, eb);
     // deposit: option 0 = wave-pruned windows, 1 = whole components, 2 = zero-skipping
@@ -1180,7 +1217,7 @@ void split_step(Ctx &c, const StepCtx &S) {
                            X.tabS);
     timing_end(c, 2, t1);
     hipEvent_t t2 = timing_begin(c);
-    hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(SST), X.lds_bytes, c.st, P, S, X.items, X.nitems, X.next,
+    hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(SST), X.lds_bytes, c.st, P, S, X.items, X.qstart, X.qnext, X.nslab,
                        IOPair{{species_io(c, 0, cur, X.s[0].bin_slots), species_io(c, 1, cur, X.s[1].bin_slots)}}, f,
                        c.Ji[0], c.Ji[1], c.Ji[2], c.dflags, X.tabA, X.tabC, X.tabS);
     hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1],
