@@ -411,10 +411,15 @@ void orc_b_half(orc_sim *s) {
             }
 }
 
-/* E <- E + dt (curl B - J).  Open z: Ex, Ey on the face planes l = 0 and
- * l = nz-1 come from the first-order Mur condition
- *   E(0)^{n+1} = E(1)^n + (dt - 1)/(dt + 1) (E(1)^{n+1} - E(0)^n)
- * (and its mirror), Ez on the outside half plane nz-1 stays untouched. */
+/* E <- E + dt (curl B - J).  Open z: Ex, Ey on the back face l = 0 come from
+ * the first-order Mur condition
+ *   E(0)^{n+1} = E(1)^n + (dt - 1)/(dt + 1) (E(1)^{n+1} - E(0)^n),
+ * and on the front face l = nz-1 from its mirror when the window is at rest.
+ * A moving window's front face keeps its tangential E (zero: the planes enter
+ * empty) -- fields reach it only by outrunning a window moving at nearly c,
+ * and a static-face Mur condition at a face that jumps forward every step or
+ * two is unstable with plasma streaming in.  Ez on the outside half plane
+ * nz-1 stays untouched. */
 void orc_e_update(orc_sim *s) {
     real *Bx = s->B[0], *By = s->B[1], *Bz = s->B[2];
     int64_t pl = (int64_t)s->nx * s->ny;
@@ -439,13 +444,14 @@ void orc_e_update(orc_sim *s) {
             }
     if (!s->periodic_z) {
         double cm = (s->dt - 1.0) / (s->dt + 1.0);
+        int front_mur = s->bw <= 0.0;
         for (int c = 0; c < 2; ++c) {
             real *o0 = keep + (0 + c) * pl, *o1 = keep + (2 + c) * pl;
             real *o2 = keep + (4 + c) * pl, *o3 = keep + (6 + c) * pl;
             real *F = s->E[c];
             for (int64_t q = 0; q < pl; ++q) {
                 F[q] = o1[q] + cm * (F[pl + q] - o0[q]);
-                F[(s->nz - 1) * pl + q] = o2[q] + cm * (F[(s->nz - 2) * pl + q] - o3[q]);
+                if (front_mur) F[(s->nz - 1) * pl + q] = o2[q] + cm * (F[(s->nz - 2) * pl + q] - o3[q]);
             }
         }
         free(keep);
@@ -1023,6 +1029,7 @@ static void e_update_adj(const orc_sim *s, real *lE[3], real *lB[3], real *lJ[3]
     }
     if (!s->periodic_z) {
         double cm = (dt - 1.0) / (dt + 1.0);
+        int front_mur = s->bw <= 0.0;
         for (int c = 0; c < 2; ++c)
             for (int64_t q = 0; q < pl; ++q) {
                 real g0 = lE[c][q]; /* E(0) = E^n(1) + cm (E^{n+1}(1) - E^n(0)) */
@@ -1032,9 +1039,12 @@ static void e_update_adj(const orc_sim *s, real *lE[3], real *lB[3], real *lJ[3]
                 lE[c][q] = 0.0;
                 int64_t t = (s->nz - 1) * pl + q, u = (s->nz - 2) * pl + q;
                 real g1 = lE[c][t];
-                lE[c][u] += cm * g1;
-                lEn[c][u] += g1;
-                lEn[c][t] += -cm * g1;
+                if (front_mur) {
+                    lE[c][u] += cm * g1;
+                    lEn[c][u] += g1;
+                    lEn[c][t] += -cm * g1;
+                } else
+                    lEn[c][t] += g1; /* front face kept */
                 lE[c][t] = 0.0;
             }
     }

@@ -194,6 +194,18 @@ class Sim:
         v = self._view(self.L.orc_field(self.h, k), self.nc, self.dtype)
         return v.reshape(self.cfg.nz, self.cfg.ny, self.cfg.nx)
 
+    def gather(self, X) -> tuple:
+        """E, B at absolute boosted position X (cells) from the current field arrays."""
+        X = np.ascontiguousarray(X, self.dtype)
+        E = np.zeros(3, self.dtype)
+        B = np.zeros(3, self.dtype)
+        self.L.orc_gather(self.h, X.ctypes.data, E.ctypes.data, B.ctypes.data)
+        return E, B
+
+    def b_half(self):
+        """One half step of the Yee B update on the current fields."""
+        self.L.orc_b_half(self.h)
+
     def particles(self, species: int, view: bool = False) -> dict:
         """Particle arrays of a species (0 beam, 1 plasma): copies, or writable
         views valid while the simulation lives when ``view`` is set."""

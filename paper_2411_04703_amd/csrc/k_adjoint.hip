@@ -48,7 +48,7 @@ __device__ inline int plane_of(const Params &P, int64_t o, int k0r, int &i, int 
 
 // adjoint of the E^{n+1} values produced by the interior update (Mur terms folded in)
 __device__ inline double lam_eff(const Params &P, const double *lE, int c, int i, int j, int l, int k0r, int shift,
-                                 double cm) {
+                                 int fm, double cm) {
     if (l < 0 || l >= P.nz) return 0.0;
     int p = ring_plane(l, k0r, P.nz);
     int64_t o = cell_index(P, i, j, p);
@@ -56,11 +56,12 @@ __device__ inline double lam_eff(const Params &P, const double *lE, int c, int i
     if (l == 0 || l == P.nz - 1) return 0.0;
     double v = lE[o];
     if (l == 1 && !shift) v += cm * lE[cell_index(P, i, j, ring_plane(0, k0r, P.nz))];
-    if (l == P.nz - 2) v += cm * lE[cell_index(P, i, j, ring_plane(P.nz - 1, k0r, P.nz))];
+    if (l == P.nz - 2 && fm) v += cm * lE[cell_index(P, i, j, ring_plane(P.nz - 1, k0r, P.nz))];
     return v;
 }
 
-__global__ void __launch_bounds__(AT) k_adj_e(Params P, int k0r, int shift, double cm, const double *lEx,
+// fm: the forward applied the Mur condition at the front face (window at rest)
+__global__ void __launch_bounds__(AT) k_adj_e(Params P, int k0r, int shift, int fm, double cm, const double *lEx,
                                               const double *lEy, const double *lEz, double *nEx, double *nEy,
                                               double *nEz, double *lBx, double *lBy, double *lBz, double *Jx,
                                               double *Jy, double *Jz) {
@@ -73,25 +74,25 @@ __global__ void __launch_bounds__(AT) k_adj_e(Params P, int k0r, int shift, doub
     double dt = P.dt;
     double e[3];
     for (int c = 0; c < 3; ++c) {
-        e[c] = lam_eff(P, lE[c], c, i, j, l, k0r, shift, cm);
+        e[c] = lam_eff(P, lE[c], c, i, j, l, k0r, shift, fm, cm);
         double n = e[c];
         if (c < 2) {
             if (l == 0 && !shift) n += -cm * lE[c][o];
             if (l == 1 && !shift) n += lE[c][cell_index(P, i, j, ring_plane(0, k0r, P.nz))];
-            if (l == P.nz - 1) n += -cm * lE[c][o];
-            if (l == P.nz - 2) n += lE[c][cell_index(P, i, j, ring_plane(P.nz - 1, k0r, P.nz))];
+            if (l == P.nz - 1) n += fm ? -cm * lE[c][o] : lE[c][o];  // Mur, or the face kept
+            if (l == P.nz - 2 && fm) n += lE[c][cell_index(P, i, j, ring_plane(P.nz - 1, k0r, P.nz))];
         } else if (l == P.nz - 1)
             n += lE[2][o];  // untouched outside half plane
         nE[c][o] = n;
         J[c][o] = -dt * e[c];
     }
     // lam_B += dt * (transpose of the curl of B in the E update)
-    double ex_l1 = lam_eff(P, lEx, 0, i, j, l + 1, k0r, shift, cm);
-    double ey_l1 = lam_eff(P, lEy, 1, i, j, l + 1, k0r, shift, cm);
-    double ez_j1 = lam_eff(P, lEz, 2, i, j + 1, l, k0r, shift, cm);
-    double ez_i1 = lam_eff(P, lEz, 2, i + 1, j, l, k0r, shift, cm);
-    double ex_j1 = lam_eff(P, lEx, 0, i, j + 1, l, k0r, shift, cm);
-    double ey_i1 = lam_eff(P, lEy, 1, i + 1, j, l, k0r, shift, cm);
+    double ex_l1 = lam_eff(P, lEx, 0, i, j, l + 1, k0r, shift, fm, cm);
+    double ey_l1 = lam_eff(P, lEy, 1, i, j, l + 1, k0r, shift, fm, cm);
+    double ez_j1 = lam_eff(P, lEz, 2, i, j + 1, l, k0r, shift, fm, cm);
+    double ez_i1 = lam_eff(P, lEz, 2, i + 1, j, l, k0r, shift, fm, cm);
+    double ex_j1 = lam_eff(P, lEx, 0, i, j + 1, l, k0r, shift, fm, cm);
+    double ey_i1 = lam_eff(P, lEy, 1, i + 1, j, l, k0r, shift, fm, cm);
     lBx[o] += dt * (e[1] - ey_l1 - e[2] + ez_j1);
     lBy[o] += dt * (-e[0] + ex_l1 + e[2] - ez_i1);
     lBz[o] += dt * (e[0] - ex_j1 - e[1] + ey_i1);
@@ -537,7 +538,8 @@ pic_status adjoint_step(Ctx &c, double *lam, double grad[2]) {
     // E update with Mur faces
     double cm = (P.dt - 1.0) / (P.dt + 1.0);
     int nb = nblocks(P.nc, AT);
-    hipLaunchKernelGGL(k_adj_e, dim3(nb), dim3(AT), 0, c.st, P, S.k0r, S.shift, cm, lE[0], lE[1], lE[2], nE[0], nE[1],
+    hipLaunchKernelGGL(k_adj_e, dim3(nb), dim3(AT), 0, c.st, P, S.k0r, S.shift, (int)(c.bw <= 0.0), cm, lE[0], lE[1],
+                       lE[2], nE[0], nE[1],
                        nE[2], lB[0], lB[1], lB[2], c.J64[0], c.J64[1], c.J64[2]);
     // second half step
     hipLaunchKernelGGL(k_adj_bhalf, dim3(nb), dim3(AT), 0, c.st, P, S.k0r, 0.5 * P.dt, lB[0], lB[1], lB[2], nE[0],

@@ -80,11 +80,15 @@ __global__ void __launch_bounds__(256) k_eupdate(Params P, int k0r, FieldsT<T> f
 }
 
 // Mur faces (tangential E on logical planes 0 and nz-1) from the saved
-// pre-update planes; when the window shifts after this step, the back plane
-// becomes the new (empty) front plane instead: E and B there are zeroed.
-// Also clears the ion current profile for the next step.
+// pre-update planes -- the front face only while the window is at rest: a
+// moving window's front keeps its tangential E (zero; the planes enter empty),
+// since a static-face Mur condition at a face that jumps forward every step or
+// two is unstable with plasma streaming in.  When the window shifts after this
+// step, the back plane becomes the new (empty) front plane instead: E and B
+// there are zeroed.  Also clears the ion current profile for the next step.
 template <typename T, typename JT>
-__global__ void k_mur_shift(Params P, int k0r, int shift, FieldsT<T> f, const T *murbuf, JT *jion, T cm) {
+__global__ void k_mur_shift(Params P, int k0r, int shift, int front_mur, FieldsT<T> f, const T *murbuf, JT *jion,
+                            T cm) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s < P.nz) jion[s] = JT(0);
     if (s >= P.plane) return;
@@ -96,7 +100,7 @@ __global__ void k_mur_shift(Params P, int k0r, int shift, FieldsT<T> f, const T 
         const T *o2 = murbuf + (4 + c) * pl, *o3 = murbuf + (6 + c) * pl;
         T *F = f.E[c];
         if (!shift) F[p0 * pl + s] = o1[s] + cm * (F[p1 * pl + s] - o0[s]);
-        F[pt * pl + s] = o2[s] + cm * (F[pm * pl + s] - o3[s]);
+        if (front_mur) F[pt * pl + s] = o2[s] + cm * (F[pm * pl + s] - o3[s]);
     }
     if (shift) {
         for (int c = 0; c < 3; ++c) {
@@ -118,12 +122,12 @@ void launch_eupdate(const Params &P, int k0r, FieldsT<T> f, JT *J[3], const JT *
 }
 
 template <typename T, typename JT>
-void launch_mur_shift(const Params &P, int k0r, int shift, FieldsT<T> f, const T *murbuf, JT *jion, T dt,
-                      hipStream_t st) {
+void launch_mur_shift(const Params &P, int k0r, int shift, int front_mur, FieldsT<T> f, const T *murbuf, JT *jion,
+                      T dt, hipStream_t st) {
     int64_t n = P.plane > P.nz ? P.plane : P.nz;
     T cm = (dt - T(1)) / (dt + T(1));
-    hipLaunchKernelGGL((k_mur_shift<T, JT>), dim3(nblocks(n, 256)), dim3(256), 0, st, P, k0r, shift, f, murbuf,
-                       jion, cm);
+    hipLaunchKernelGGL((k_mur_shift<T, JT>), dim3(nblocks(n, 256)), dim3(256), 0, st, P, k0r, shift, front_mur, f,
+                       murbuf, jion, cm);
 }
 
 template void launch_bhalf<double>(const Params &, int, FieldsT<double>, double, double *, hipStream_t);
@@ -132,9 +136,9 @@ template void launch_eupdate<double, double>(const Params &, int, FieldsT<double
                                              double, hipStream_t);
 template void launch_eupdate<float, long long>(const Params &, int, FieldsT<float>, long long *[3],
                                                const long long *, float, hipStream_t);
-template void launch_mur_shift<double, double>(const Params &, int, int, FieldsT<double>, const double *, double *,
+template void launch_mur_shift<double, double>(const Params &, int, int, int, FieldsT<double>, const double *, double *,
                                                double, hipStream_t);
-template void launch_mur_shift<float, long long>(const Params &, int, int, FieldsT<float>, const float *,
+template void launch_mur_shift<float, long long>(const Params &, int, int, int, FieldsT<float>, const float *,
                                                  long long *, float, hipStream_t);
 
 // ---------------------------------------------------------------- ion current

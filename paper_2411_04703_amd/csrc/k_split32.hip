@@ -66,13 +66,15 @@ struct SplitState {
 
 static SplitState &SS(Ctx &c) { return *static_cast<SplitState *>(c.split); }
 
-static int lds_bytes_of(const Params &P, int &ebytes) {
-    int nE = (P.tx + 3) * (P.ty + 3) * (P.tz + 3);
-    int nJ = (P.tx + 4) * (P.ty + 5) * (P.tz + 5) + (P.tx + 5) * (P.ty + 4) * (P.tz + 5) +
-             (P.tx + 5) * (P.ty + 5) * (P.tz + 4);
-    ebytes = (6 * nE * 4 + 15) & ~15;
-    return ebytes + 8 * nJ + 16 * (P.tz + 3);
+// LDS of one step-kernel workgroup: E box (T+4)^3 and B box (T+3)^3 in FP32,
+// the three int64 current boxes, the undulator phase table
+int split_lds_bytes(int tx, int ty, int tz) {
+    int nF = (tx + 4) * (ty + 4) * (tz + 4), nE = (tx + 3) * (ty + 3) * (tz + 3);
+    int nJ = (tx + 4) * (ty + 5) * (tz + 5) + (tx + 5) * (ty + 4) * (tz + 5) + (tx + 5) * (ty + 5) * (tz + 4);
+    return ((3 * nF * 4 + 3 * nE * 4 + 15) & ~15) + 8 * nJ + 16 * (tz + 3);
 }
+
+static int lds_bytes_of(const Params &P) { return split_lds_bytes(P.tx, P.ty, P.tz); }
 
 // ---------------------------------------------------------------- helpers
 // The particle and bin arrays are device (global) memory: accessed through
@@ -407,12 +409,43 @@ __device__ inline bool renormalise(const Params &P, const StepCtx &S, PState &q)
 // out explicitly where wanted.
 
 // field value accessors: staged LDS box (tiled) or ring-buffered global arrays (untiled)
+// The B update of one node from E at the node and its +x, +y, +z neighbours
+// (strides sx, sy, sz): dB = -h curl E, Bx and By untouched on the last
+// logical plane.  The tiled and the untiled path both call this, so B^n is the
+// same wherever a particle is handled.
+__device__ inline void half_curl_b(const float *ex, const float *ey, const float *ez, int64_t sx, int64_t sy,
+                                   int64_t sz, bool last_plane, float h, float dB[3]) {
+    const float x0 = ex[0], y0 = ey[0], z0 = ez[0];
+    dB[0] = last_plane ? 0.0f : -(h * ((ez[sy] - z0) - (ey[sz] - y0)));
+    dB[1] = last_plane ? 0.0f : -(h * ((ex[sz] - x0) - (ez[sx] - z0)));
+    dB[2] = -(h * ((ey[sx] - y0) - (ex[sy] - x0)));
+}
+
 struct GlobalField {
     const Params *P;
-    const float *const *F;  // E0 E1 E2 B0 B1 B2
+    const float *const *F;  // E0 E1 E2 B0 B1 B2 (B at n - 1/2)
     int i0, j0, l0, k0r;    // cell of the particle (indices relative to it)
+    float hb;               // dt / 2
+    __device__ float e(int comp, int i, int j, int l) const {
+        return F[comp][cell_index(*P, i, j, ring_plane(l, k0r, P->nz))];
+    }
     __device__ float at(int comp, int x, int y, int z) const {
-        return F[comp][cell_index(*P, i0 + x, j0 + y, ring_plane(l0 + z, k0r, P->nz))];
+        const int i = i0 + x, j = j0 + y, l = l0 + z;
+        if (comp < 3) return e(comp, i, j, l);
+        // B^n from B^(n-1/2) and E^n, exactly as the tiled staging forms it
+        float ex[2][2][2], ey[2][2][2], ez[2][2][2];  // [dz][dy][dx], only the needed corners filled
+        ex[0][0][0] = e(0, i, j, l);
+        ey[0][0][0] = e(1, i, j, l);
+        ez[0][0][0] = e(2, i, j, l);
+        ex[1][0][0] = e(0, i, j, l + 1);
+        ex[0][1][0] = e(0, i, j + 1, l);
+        ey[1][0][0] = e(1, i, j, l + 1);
+        ey[0][0][1] = e(1, i + 1, j, l);
+        ez[0][1][0] = e(2, i, j + 1, l);
+        ez[0][0][1] = e(2, i + 1, j, l);
+        float dB[3];
+        half_curl_b(&ex[0][0][0], &ey[0][0][0], &ez[0][0][0], 1, 2, 4, l == P->nz - 1, hb, dB);
+        return e(comp, i, j, l) + dB[comp - 3];
     }
 };
 
@@ -475,7 +508,7 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
         atomicOr(flags, DFLAG_NONFINITE);
         return false;
     }
-    GlobalField gf{&P, F6, q.i, q.j, q.l, S.k0r};
+    GlobalField gf{&P, F6, q.i, q.j, q.l, S.k0r, (float)(0.5 * P.dt)};
     float EB[6];
     gather6(gf, q.o, 0, 0, 0, EB);
     double a_l = 0.0;
@@ -512,21 +545,25 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
 // and the deposit is one per-particle base address plus an immediate offset),
 // ST threads, 2 waves per SIMD.  DEP selects the deposit variant (esk_component).
 template <int TX, int TY, int TZ> struct TileGeom {
-    static constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3, NE = EX * EY * EZ;  // E, B boxes (t0 - 1 ...)
+    static constexpr int EX = TX + 3, EY = TY + 3, EZ = TZ + 3, NE = EX * EY * EZ;  // B box (t0 - 1 ...)
+    static constexpr int FX = TX + 4, FY = TY + 4, FZ = TZ + 4, NF = FX * FY * FZ;  // E box (t0 - 1 ...), one more
+                                                                                    // node for the curl at B sites
     // current boxes (origin t0 - 2): along their own axis TX + 4, across TX + 5
     static constexpr int XX = TX + 4, XY = TY + 5, XZ = TZ + 5;
     static constexpr int YX = TX + 5, YY = TY + 4, YZ = TZ + 5;
     static constexpr int ZX = TX + 5, ZY = TY + 5, ZZ = TZ + 4;
     static constexpr int NJX = XX * XY * XZ, NJY = YX * YY * YZ, NJZ = ZX * ZY * ZZ, NJ = NJX + NJY + NJZ;
     static constexpr int NTAB = TZ + 3;
-    static constexpr int EBYTES = (6 * NE * 4 + 15) & ~15;
+    static constexpr int EBYTES = (3 * NF * 4 + 3 * NE * 4 + 15) & ~15;
     static constexpr int LDS = EBYTES + 8 * NJ + 16 * NTAB;
 };
 
-template <int EX, int EY, int NE> struct LdsBoxT {
-    const float *F;  // 6 boxes of NE floats; box index of (half-)node k (relative to t0) is k + 1
+template <class G> struct LdsBoxT {
+    const float *F;  // 3 E boxes of G::NF floats, then 3 B boxes of G::NE; box index of (half-)node k
+                     // (relative to t0) is k + 1
     __device__ float at(int comp, int x, int y, int z) const {
-        return F[comp * NE + (x + 1) + EX * ((y + 1) + EY * (z + 1))];
+        return comp < 3 ? F[comp * G::NF + (x + 1) + G::FX * ((y + 1) + G::FY * (z + 1))]
+                        : F[3 * G::NF + (comp - 3) * G::NE + (x + 1) + G::EX * ((y + 1) + G::EY * (z + 1))];
     }
 };
 
@@ -544,6 +581,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
     double *tabA = (double *)(Js + G::NJ);
     float *tabC = (float *)(tabA + G::NTAB), *tabS = tabC + G::NTAB;
     const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
+    const float hb = (float)(0.5 * P.dt);
     // slab queue of this workgroup's XCD first, then the others' (work stealing)
     int q = (int)(blockIdx.x % (unsigned)nslab), hops = 0;
 
@@ -577,14 +615,34 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
         const int t0x = (bin % P.ntx) * TX, t0y = ((bin / P.ntx) % P.nty) * TY, t0z = (bin / (P.ntx * P.nty)) * TZ;
         const int64_t b0 = gbl(IO.in_off)[bin];
         const int end = min(cnt, start + CH);
-        // stage E, B: box node (a, b, c) <-> absolute node (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)
-        for (int k = tid; k < G::NE; k += SST) {
-            const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
+        // stage E^n and B^(n-1/2): box node (a, b, c) <-> absolute node (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)
+        for (int k = tid; k < G::NF; k += SST) {
+            const int bc = k / G::FX, a = k - bc * G::FX, c = bc / G::FY, b = bc - c * G::FY;
             int l = t0z - 1 + c;
             l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
             const int64_t o = near_cell(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
-            for (int q = 0; q < 6; ++q) Fs[q * G::NE + k] = F6[q][o];
+            for (int q = 0; q < 3; ++q) Fs[q * G::NF + k] = F6[q][o];
+        }
+        float *Bs = Fs + 3 * G::NF;
+        for (int k = tid; k < G::NE; k += SST) {
+            const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
+            int l = t0z - 1 + c;
+            l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);
+            const int64_t o = near_cell(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Bs[q * G::NE + k] = F6[3 + q][o];
+        }
+        __syncthreads();
+        // B^n = B^(n-1/2) - (dt/2) curl E^n on the B box (the first half of the Yee B update)
+        for (int k = tid; k < G::NE; k += SST) {
+            const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
+            const float *ex = Fs + a + G::FX * (b + G::FY * c), *ey = ex + G::NF, *ez = ey + G::NF;
+            float B3[3];
+            half_curl_b(ex, ey, ez, 1, G::FX, G::FX * G::FY, t0z - 1 + c == P.nz - 1, hb, B3);
+            Bs[k] += B3[0];
+            Bs[G::NE + k] += B3[1];
+            Bs[2 * G::NE + k] += B3[2];
         }
         for (int k = tid; k < G::NJ; k += SST) Js[k] = 0;
         if (P.und_kind)
@@ -595,7 +653,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
             }
         __syncthreads();
 
-        const LdsBoxT<G::EX, G::EY, G::NE> box{Fs};
+        const LdsBoxT<G> box{Fs};
         for (int base = start; base < end; base += SST) {
             bool act = base + tid < end;
             PState q;
@@ -924,8 +982,7 @@ void split_setup(Ctx &c) {
     X->qnext = (int32_t *)(((uintptr_t)(X->tabS + P.nz + 2) + 15) & ~(uintptr_t)15);
     X->qstart = X->qnext + 16;
     X->nslab = P.ntz % 8 == 0 ? 8 : 1;  // workgroups are dispatched round-robin over the 8 XCDs
-    int eb;
-    X->lds_bytes = lds_bytes_of(P, eb);
+    X->lds_bytes = lds_bytes_of(P);
     // deposit: option 0 = wave-pruned windows, 1 = whole components, 2 = zero-skipping
     X->kern = step_kernel(P.tx, P.ty, P.tz, c.opt.variant == 0 ? 2 : (c.opt.variant == 1 ? 1 : 0));
     const void *kern = (const void *)X->kern;
@@ -1207,9 +1264,8 @@ void split_step(Ctx &c, const StepCtx &S) {
         f.B[k] = c.B32[k];
     }
     int cur = c.cur32;
-    hipEvent_t t0 = timing_begin(c);
-    launch_bhalf<float>(P, S.k0r, f, (float)(0.5 * P.dt), nullptr, c.st);
-    timing_end(c, 1, t0);
+    // the first B half step is formed inside the particle kernel (B^n in LDS); the field state between
+    // steps stays (E^n, B^(n-1/2)), and after the push one full B step replaces the two halves
     hipEvent_t t1 = timing_begin(c);
     build_worklist(c, cur, 0, 0);  // overflow tails go to k_split_overflow
     if (P.und_kind)
@@ -1227,9 +1283,10 @@ void split_step(Ctx &c, const StepCtx &S) {
     if (P.ions) launch_ion_fixed(P, c.sh_lo, c.sh_hi - c.sh_lo, S.t, S.t1, S.k0, c.jioni, c.dflags, c.st);
     timing_end(c, 2, t3);
     hipEvent_t t4 = timing_begin(c);
-    launch_bhalf<float>(P, S.k0r, f, (float)(0.5 * P.dt), (float *)c.murbuf, c.st);
+    launch_bhalf<float>(P, S.k0r, f, (float)P.dt, (float *)c.murbuf, c.st);  // B^(n-1/2) -> B^(n+1/2)
     launch_eupdate<float, long long>(P, S.k0r, f, c.Ji, c.jioni, (float)P.dt, c.st);
-    launch_mur_shift<float, long long>(P, S.k0r, S.shift, f, (const float *)c.murbuf, c.jioni, (float)P.dt, c.st);
+    launch_mur_shift<float, long long>(P, S.k0r, S.shift, c.bw <= 0.0, f, (const float *)c.murbuf, c.jioni,
+                                       (float)P.dt, c.st);
     timing_end(c, 1, t4);
 }
 

@@ -155,10 +155,7 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
         P.lgy = lg(t[1]);
         P.lgz = lg(t[2]);
         // LDS of one workgroup: staged E, B (+halo) in FP32, int64 current boxes, field table
-        int nE = (t[0] + 3) * (t[1] + 3) * (t[2] + 3);
-        int nJ = (t[0] + 4) * (t[1] + 5) * (t[2] + 5) + (t[0] + 5) * (t[1] + 4) * (t[2] + 5) +
-                 (t[0] + 5) * (t[1] + 5) * (t[2] + 4);
-        if (((6 * nE * 4 + 15) & ~15) + 8 * nJ + 16 * (t[2] + 3) > 160 * 1024)
+        if (split_lds_bytes(t[0], t[1], t[2]) > 160 * 1024)
             return fail(err, PIC_EINVAL, "options: tile too large for 160 KiB of LDS");
         P.tx = t[0];
         P.ty = t[1];
@@ -398,7 +395,8 @@ static pic_status step64(Ctx &c) {
     hipEvent_t t3 = timing_begin(c);
     launch_bhalf<double>(P, S.k0r, f, 0.5 * P.dt, (double *)c.murbuf, c.st);
     launch_eupdate<double, double>(P, S.k0r, f, c.J64, c.jion64, P.dt, c.st);
-    launch_mur_shift<double, double>(P, S.k0r, S.shift, f, (const double *)c.murbuf, c.jion64, P.dt, c.st);
+    launch_mur_shift<double, double>(P, S.k0r, S.shift, c.bw <= 0.0, f, (const double *)c.murbuf, c.jion64, P.dt,
+                                     c.st);
     timing_end(c, 1, t3);
     c.step += 1;
     c.k0 = S.k0n;

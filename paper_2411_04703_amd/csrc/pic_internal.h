@@ -99,8 +99,8 @@ void launch_bhalf(const Params &P, int k0r, FieldsT<T> f, T h, T *murbuf, hipStr
 template <typename T, typename JT>
 void launch_eupdate(const Params &P, int k0r, FieldsT<T> f, JT *J[3], const JT *jion, T dt, hipStream_t st);
 template <typename T, typename JT>
-void launch_mur_shift(const Params &P, int k0r, int shift, FieldsT<T> f, const T *murbuf, JT *jion, T dt,
-                      hipStream_t st);
+void launch_mur_shift(const Params &P, int k0r, int shift, int front_mur, FieldsT<T> f, const T *murbuf, JT *jion,
+                      T dt, hipStream_t st);
 void launch_ion64(const Params &P, int64_t sh_lo, int64_t nsheets, double t0, double t1, int64_t k0, double *jion,
                   hipStream_t st);
 void launch_ion_fixed(const Params &P, int64_t sh_lo, int64_t nsheets, double t0, double t1, int64_t k0,
@@ -118,6 +118,7 @@ int64_t compact64(Ctx &c, Part64 src, Part64 dst, int64_t n);  // returns surviv
 // FP32 split particles (k_split32.hip)
 void split_setup(Ctx &c);
 bool split_tile_supported(int tx, int ty, int tz);  // tiles the FP32 step kernel is built for
+int split_lds_bytes(int tx, int ty, int tz);         // LDS of one FP32 step-kernel workgroup
 uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes);
 pic_status split_copy_state(Ctx &c, char *dev, bool save);  // snapshot <-> context (device buffer)
 void split_free(Ctx &c);

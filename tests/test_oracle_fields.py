@@ -88,3 +88,21 @@ def test_mur_3d_normal_incidence_reflection_small():
     s.step(int(100 / dt))
     e1 = (s.field("Ex") ** 2).sum()
     assert e1 < 1e-3 * e0
+
+
+def test_moving_window_with_plasma_is_stable():
+    """A small random field seeded into a cold plasma streaming through a window
+    that moves at nearly c must not grow.  (A static-face Mur condition applied
+    at the moving front face made a face mode grow ~1e5-fold per 20 steps.)"""
+    w = pin.scaled(pin.adjoint_subcase(), nx=8, ny=8, nz=64, n_beam=16)
+    w["beam"]["charge_C"] = 1e-30
+    s = po.Sim(w, pin.beam_normals(16))
+    assert s.info().bw > 0.99
+    rng = np.random.default_rng(3)
+    for f in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        s.field(f)[:] = 1e-12 * rng.standard_normal(s.field(f).shape)
+    e = []
+    for _ in range(8):
+        s.step(20)
+        e.append(s.diag(1.0)["field_energy"])
+    assert max(e) < 1e-19, e
