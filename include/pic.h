@@ -124,8 +124,11 @@ typedef struct {
  *       16x8x8, 8x8x16, 8x8x8, 16x8x4, 8x8x4 that divides the grid.
  * max_steps: sizing of the plasma capacity of the FP64 mode (injection between
  *            compactions, or over the whole run when record = 1).
- * record: 1 keeps particle slots stable (no compaction) so that
- *         pic_adjoint_step() can follow them; FP64 mode only.
+ * record: FP64 mode: 1 keeps particle slots stable (no compaction) so that
+ *         pic_adjoint_step() can follow them.  FP32 mode: 1 gives every
+ *         particle a 4-byte id, its slot in the FP64 record layout of the same
+ *         configuration, so that pic_state_to_fp64() can hand the state to an
+ *         FP64 record context (the adjoint of an FP32 run).
  * variant: current deposition of the FP32 particle kernel: 0 = the Esirkepov
  *          window pruned per wave of 64 particles (its last node along an axis
  *          only when some particle of the wave crosses a half cell there),
@@ -209,6 +212,17 @@ PIC_API pic_status pic_read(pic_ctx *c, int32_t which, void *dst, int64_t *count
 /* Overwrite named arrays (same layouts as pic_read, src on the DEVICE):
  * fields, and particle phase space of existing slots (FP64 mode). */
 PIC_API pic_status pic_write(pic_ctx *c, int32_t which, const void *src, int64_t count);
+
+/* FP32-mode adjoint support: overwrite the dynamic state of dst (FP64 mode,
+ * record = 1) with the state of src (FP32 mode, record = 1, same
+ * configuration): fields widened to FP64, every particle written to its slot
+ * (its id) as absolute position, momentum and weight, slots without a particle
+ * dead, window origin, step and injection cursors copied.  dst's
+ * options.max_steps must cover src's run (PIC_ENOMEM otherwise); PIC_EINVAL
+ * for other precisions or a differing configuration.  Synchronous.  After it,
+ * pic_adjoint_seed_bunching() / pic_adjoint_step() on dst linearise about the
+ * FP32 trajectory. */
+PIC_API pic_status pic_state_to_fp64(const pic_ctx *src, pic_ctx *dst);
 
 /* Checkpoint: copy the full dynamic state (particles, fields, window origin,
  * step counter, injection cursors; FP32 mode also its bin layout) into / out

@@ -133,7 +133,7 @@ struct IOPair {
 
 // append (active lanes) to bin `bin` of the output store; overflow tail when the bin is full
 __device__ inline void append(const OutStore &O, bool active, int bin, int cell, const float o[3], const float u[3],
-                              float w, int32_t *flags) {
+                              float w, int32_t *flags, int id) {
     int r = reserve_slot(active, active ? bin : 0, O.cnt);
     if (!active) return;
     int64_t b0 = gbl(O.off)[bin], cap = gbl(O.off)[bin + 1] - b0;
@@ -157,6 +157,7 @@ __device__ inline void append(const OutStore &O, bool active, int bin, int cell,
     gbl(b.uy)[s] = u[1];
     gbl(b.uz)[s] = u[2];
     gbl(b.w)[s] = w;
+    if (b.id) gbl(b.id)[s] = id;
 }
 
 __device__ inline int bin_of(const Params &P, int i, int j, int l) {
@@ -208,6 +209,7 @@ __device__ inline bool fixed_ok(float f, double fscale) {
 struct PState {
     int i, j, l;
     float o[3], u[3], w;
+    int id;  // record mode only
 };
 
 __device__ inline void load_particle(const Part32 &in, int64_t s, const Params &P, PState &q) {
@@ -219,6 +221,7 @@ __device__ inline void load_particle(const Part32 &in, int64_t s, const Params &
     q.u[1] = gbl(in.uy)[s];
     q.u[2] = gbl(in.uz)[s];
     q.w = gbl(in.w)[s];
+    q.id = in.id ? gbl(in.id)[s] : 0;
 }
 
 // undulator field at logical plane l: the plane's phase and envelope argument in
@@ -699,7 +702,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                 }
             }
             append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags);
+                   q.u, q.w, flags, q.id);
         }
         __syncthreads();
         // flush nonzero LDS currents with global 64-bit integer atomics
@@ -773,7 +776,7 @@ __global__ void __launch_bounds__(256) k_split_overflow(Params P, StepCtx S, con
                 act = particle_global(P, S, F6, Jx, Jy, Jz, q, flags);
             }
             append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags);
+                   q.u, q.w, flags, q.id);
         }
     }
 }
@@ -801,7 +804,7 @@ __global__ void __launch_bounds__(ST) k_rebin(Params P, const int4 *items, const
             PState q;
             if (act) load_particle(IO.in, b0 + k, P, q);
             append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags);
+                   q.u, q.w, flags, q.id);
         }
     }
 }
@@ -927,9 +930,13 @@ static SpeciesIO species_io(Ctx &c, int sp, int cur, int64_t in_ovf_start) {
 }
 
 // ---------------------------------------------------------------- setup
-static Part32 carve32(char *base, int64_t slots) {
+// one particle buffer: 8 arrays of 4 B per slot, plus the id array in record mode
+static uint64_t slot_bytes(const Ctx &c) { return c.record ? 36 : 32; }
+
+static Part32 carve32(char *base, int64_t slots, bool ids) {
     Part32 p;
     uint64_t n = (uint64_t)slots;
+    p.id = ids ? (int32_t *)(base + 32 * n) : nullptr;
     p.cell = (int32_t *)base;
     float *f = (float *)(base + 4 * n);
     p.ox = f;
@@ -954,8 +961,8 @@ void split_setup(Ctx &c) {
         s.ovf_cap = sp ? c.ovf_cap_p : c.ovf_cap_b;
         int64_t slots = s.bin_slots + s.ovf_cap;
         char *b = A + (sp ? c.split_off_p : c.split_off_b);
-        s.buf[0] = carve32(b, slots);
-        s.buf[1] = carve32(b + 32 * (uint64_t)slots, slots);
+        s.buf[0] = carve32(b, slots, c.record);
+        s.buf[1] = carve32(b + slot_bytes(c) * (uint64_t)slots, slots, c.record);
     }
     char *bins = A + c.split_off_bins;
     int64_t *offs = (int64_t *)bins;
@@ -1069,6 +1076,7 @@ __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, d
         flat.uy[r] = s.u[1];
         flat.uz[r] = s.u[2];
         flat.w[r] = s.w;
+        if (flat.id) flat.id[r] = (int)q;  // beam slot = beam index
     }
     red[0][threadIdx.x] = cnt;
     red[1][threadIdx.x] = vzs;
@@ -1089,7 +1097,7 @@ __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, d
 // plasma sheets [l0, l0 + nsheets) at time t, window origin k0: appended to bins
 // of `out` (bins == true) or to a flat list counted by out.ovf (bins == false)
 __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_t k0, OutStore out, int bins,
-                           int32_t *flags) {
+                           int32_t *flags, int64_t id0) {
     int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
     bool act = q < total;
     PState s;
@@ -1116,11 +1124,12 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
         s.u[1] = 0.0f;
         s.u[2] = (float)(-P.uR);
         s.w = (float)w;
+        s.id = (int)(id0 + q);  // the lattice particle's FP64 record slot
         act = w != 0.0 && s.l >= 3 && s.l < P.nz - 4;
         key = act ? bin_of(P, s.i, s.j, s.l) : 0;
     }
     if (bins) {
-        append(out, act, key, act ? pack_cell(P, s.i, s.j, s.l) : 0, s.o, s.u, s.w, flags);
+        append(out, act, key, act ? pack_cell(P, s.i, s.j, s.l) : 0, s.o, s.u, s.w, flags, s.id);
     } else {
         int r = reserve_slot(act, 0, out.ovf);
         if (act) {
@@ -1132,6 +1141,7 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
             out.buf.uy[r] = s.u[1];
             out.buf.uz[r] = s.u[2];
             out.buf.w[r] = s.w;
+            if (out.buf.id) out.buf.id[r] = s.id;
         }
     }
 }
@@ -1234,12 +1244,35 @@ void split_beam_init(Ctx &c, const double *normals_dev) {
     c.bw = cnt > 0 ? vz / cnt : 0.0;
 }
 
+// inject the nonzero-weight sheets of [l0, l1) at time t: one launch per run of
+// consecutive nonzero-weight sheets, whose particles take the next ids (the
+// slots the FP64 record layout gives them, in the same order)
+static pic_status inject_runs32(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0, const OutStore &o, int bins) {
+    const Params &P = c.P;
+    const int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
+    int64_t l = l0;
+    while (l < l1) {
+        while (l < l1 && sheet_weight(P, l) == 0.0) ++l;
+        const int64_t a = l;
+        while (l < l1 && sheet_weight(P, l) != 0.0) ++l;
+        const int64_t total = (l - a) * per;
+        if (total > 0) {
+            if (c.record && c.np_slots + total > 2147483647) {
+                c.err = "record mode: more than 2^31 plasma particles over the run";
+                return PIC_ERANGE;
+            }
+            hipLaunchKernelGGL(k_inject32, dim3(nblocks(total, ST)), dim3(ST), 0, c.st, P, a, total, t, k0, o, bins,
+                               c.dflags, c.np_slots);
+            c.np_slots += total;
+        }
+    }
+    return PIC_OK;
+}
+
 pic_status split_plasma_fill(Ctx &c) {
     SplitState &X = SS(c);
     const Params &P = c.P;
     if (P.has_plasma) {
-        int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
-        int64_t total = (c.sh_hi - c.sh_lo) * per;
         OutStore o;
         o.buf = X.s[1].buf[1];
         o.off = X.s[1].off[1];
@@ -1247,9 +1280,8 @@ pic_status split_plasma_fill(Ctx &c) {
         o.ovf = X.s[1].ovf[1];
         o.bin_slots = X.s[1].bin_slots;
         o.ovf_cap = X.s[1].ovf_cap;
-        if (total > 0)
-            hipLaunchKernelGGL(k_inject32, dim3(nblocks(total, ST)), dim3(ST), 0, c.st, P, c.sh_lo, total, 0.0,
-                               (int64_t)0, o, 0, c.dflags);
+        pic_status st = inject_runs32(c, c.sh_lo, c.sh_hi, 0.0, 0, o, 0);
+        if (st != PIC_OK) return st;
     }
     return bins_from_flat(c);
 }
@@ -1291,12 +1323,11 @@ void split_step(Ctx &c, const StepCtx &S) {
 }
 
 // inject sheets [l0, l1) at time t into the output buffer (after split_step), then swap
-void split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n) {
+pic_status split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n) {
     SplitState &X = SS(c);
     const Params &P = c.P;
     int o = c.cur32 ^ 1;
     if (P.has_plasma && l1 > l0) {
-        int64_t total = (l1 - l0) * (int64_t)P.plane * P.ppx * P.ppy;
         OutStore out;
         out.buf = X.s[1].buf[o];
         out.off = X.s[1].off[o];
@@ -1304,10 +1335,50 @@ void split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n
         out.ovf = X.s[1].ovf[o];
         out.bin_slots = X.s[1].bin_slots;
         out.ovf_cap = X.s[1].ovf_cap;
-        hipLaunchKernelGGL(k_inject32, dim3(nblocks(total, ST)), dim3(ST), 0, c.st, P, l0, total, t, k0n, out, 1,
-                           c.dflags);
+        pic_status st = inject_runs32(c, l0, l1, t, k0n, out, 1);
+        if (st != PIC_OK) return st;
     }
     c.cur32 = o;
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------- record mode export
+// every particle of the current buffer to its FP64 record slot (its id):
+// absolute boosted position, momentum, weight, alive; one block per bin, the
+// last block takes the overflow tail
+__global__ void k_split_export(Params P, int64_t k0, Part32 in, const int64_t *off, const int32_t *cnt,
+                               int64_t ovf_start, const int32_t *ovf, int64_t ovf_cap, Part64 dst) {
+    const int b = blockIdx.x;
+    int64_t s0, n;
+    if (b < P.nbins) {
+        s0 = off[b];
+        n = min((int64_t)cnt[b], off[b + 1] - off[b]);
+    } else {
+        s0 = ovf_start;
+        n = min((int64_t)*ovf, ovf_cap);
+    }
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        const int64_t s = s0 + k, d = in.id[s];
+        int i, j, l;
+        unpack_cell(P, in.cell[s], i, j, l);
+        dst.x[d] = i + (double)in.ox[s];
+        dst.y[d] = j + (double)in.oy[s];
+        dst.z[d] = (double)(k0 + l) + (double)in.oz[s];
+        dst.ux[d] = in.ux[s];
+        dst.uy[d] = in.uy[s];
+        dst.uz[d] = in.uz[s];
+        dst.w[d] = in.w[s];
+        dst.alive[d] = 1;
+    }
+}
+
+void split_export64(const Ctx &c, Part64 beam, Part64 plasma, hipStream_t st) {
+    const SplitState &X = *static_cast<const SplitState *>(c.split);
+    for (int sp = 0; sp < 2; ++sp) {
+        const Store &S = X.s[sp];
+        hipLaunchKernelGGL(k_split_export, dim3(c.P.nbins + 1), dim3(256), 0, st, c.P, c.k0, S.buf[c.cur32],
+                           S.off[c.cur32], S.cnt[c.cur32], S.bin_slots, S.ovf[c.cur32], S.ovf_cap, sp ? plasma : beam);
+    }
 }
 
 // ---------------------------------------------------------------- snapshots
@@ -1316,8 +1387,9 @@ void split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n
 // each species (the other buffer is rewritten by the next step).
 static uint64_t a256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
-uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes) {
-    return 6 * a256(4 * (uint64_t)nc) + a256(32 * (uint64_t)slots_b) + a256(32 * (uint64_t)slots_p) + a256(bins_bytes);
+uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes, int record) {
+    const uint64_t sb = record ? 36 : 32;
+    return 6 * a256(4 * (uint64_t)nc) + a256(sb * (uint64_t)slots_b) + a256(sb * (uint64_t)slots_p) + a256(bins_bytes);
 }
 
 pic_status split_copy_state(Ctx &c, char *dev, bool save) {
@@ -1336,7 +1408,7 @@ pic_status split_copy_state(Ctx &c, char *dev, bool save) {
         if ((st = mv(c.B32[k], 4 * (uint64_t)c.P.nc)) != PIC_OK) return st;
     for (int sp = 0; sp < 2; ++sp) {
         Store &S = X.s[sp];
-        if ((st = mv(S.buf[c.cur32].cell, 32 * (uint64_t)(S.bin_slots + S.ovf_cap))) != PIC_OK) return st;
+        if ((st = mv(S.buf[c.cur32].cell, slot_bytes(c) * (uint64_t)(S.bin_slots + S.ovf_cap))) != PIC_OK) return st;
     }
     return mv(c.arena + c.split_off_bins, c.split_bins_bytes);
 }

@@ -68,7 +68,6 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (o->pusher < -1 || o->pusher > 1) return fail(err, PIC_EINVAL, "options: pusher");
     if (o->variant < 0 || o->variant > 2) return fail(err, PIC_EINVAL, "options: variant 0, 1 or 2");
     if (o->wg_per_cu < 0 || o->wg_per_cu > 8) return fail(err, PIC_EINVAL, "options: wg_per_cu in [0, 8]");
-    if (o->record && o->precision != PIC_FP64_PLAIN) return fail(err, PIC_EINVAL, "options: record needs FP64 mode");
 
     memset(&P, 0, sizeof P);
     memset(&d, 0, sizeof d);
@@ -233,8 +232,9 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
         pl.ovf_b = std::max<int64_t>(8192, pl.cap_b / 16);
         pl.ovf_p = std::max<int64_t>(8192, pl.cap_p / 16);
         pl.cap_b = b->n_macro;
-        off[11] = take(32 * (uint64_t)(cb + pl.ovf_b) * 2);
-        off[12] = take(32 * (uint64_t)(cp + pl.ovf_p) * 2);
+        const uint64_t sb = pl.record ? 36 : 32;  // record mode: + the particle id
+        off[11] = take(sb * (uint64_t)(cb + pl.ovf_b) * 2);
+        off[12] = take(sb * (uint64_t)(cp + pl.ovf_p) * 2);
         uint64_t bins_bytes = 8 * (uint64_t)(nbins + 1) * 4 + 4 * (uint64_t)nbins * 4 + 256;
         off[13] = take(bins_bytes);
         int64_t items_cap = (cb + cp + pl.ovf_b + pl.ovf_p) / 4096 + 2 * nbins + 64;
@@ -260,7 +260,8 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
     if (o->precision == PIC_FP64_PLAIN)
         st += al256(60 * (uint64_t)std::max<int64_t>(pl.cap_b, 1)) + al256(60 * (uint64_t)std::max<int64_t>(pl.cap_p, 1));
     else
-        st = 256 + split_state_payload(P.nc, (int64_t)off[20] + pl.ovf_b, (int64_t)off[21] + pl.ovf_p, off[23]);
+        st = 256 + split_state_payload(P.nc, (int64_t)off[20] + pl.ovf_b, (int64_t)off[21] + pl.ovf_p, off[23],
+                                       pl.record);
     pl.state = st;
     return PIC_OK;
 }
@@ -325,8 +326,7 @@ static pic_status end_of_step_sheets(Ctx &c, const StepCtx &S) {
         if (c.sh_lo > c.sh_hi) c.sh_lo = c.sh_hi;
     }
     if (c.precision == PIC_FP64_PLAIN) return c.P.has_plasma ? inject_range64(c, l0, c.sh_hi, S.t1) : PIC_OK;
-    split_inject_and_swap(c, l0, c.sh_hi, S.t1, S.k0n);  // FP32: append to the output bins, then swap
-    return PIC_OK;
+    return split_inject_and_swap(c, l0, c.sh_hi, S.t1, S.k0n);  // FP32: append to the output bins, then swap
 }
 
 static pic_status check_flags(Ctx &c) {
@@ -563,6 +563,8 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
         c->split_bins_bytes = off[23];
         c->split_off_wl = off[14];
         c->split_items_cap = (int64_t)off[24];
+        c->nb_slots = b->n_macro;  // ids: beam particle k is FP64 record slot k; plasma ids count up
+        c->np_slots = 0;
         split_setup(*c);
         if (b->n_macro > 0) split_beam_init(*c, c->stage);
     }
@@ -662,6 +664,11 @@ pic_status pic_diag(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_di
 }
 
 // copy logical planes of a field into dst (double), un-rotating the ring
+__global__ void k_f2d(const float *a, double *b, int64_t n) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) b[q] = (double)a[q];
+}
+
 __global__ void k_field_out(const void *src, int isfloat, double *dst, int64_t plane, int nz, int k0r) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= plane * nz) return;
@@ -853,6 +860,47 @@ pic_status pic_adjoint_step(pic_ctx *c, void *lam, double grad[2]) {
         return PIC_ESTATE;
     }
     return adjoint_step(*c, (double *)lam, grad);
+}
+
+pic_status pic_state_to_fp64(const pic_ctx *src, pic_ctx *dst) {
+    if (!src || !dst) return PIC_EINVAL;
+    if (src->precision != PIC_FP32_SPLIT || !src->record || dst->precision != PIC_FP64_PLAIN || !dst->record) {
+        dst->err = "pic_state_to_fp64: needs an FP32 context and an FP64 context, both with record = 1";
+        return PIC_EINVAL;
+    }
+    const Params &A = src->P, &B = dst->P;
+    if (A.nx != B.nx || A.ny != B.ny || A.nz != B.nz || A.dt != B.dt || A.gR != B.gR || A.wbeam != B.wbeam ||
+        A.wsheet != B.wsheet || A.und_kind != B.und_kind || A.pusher != B.pusher) {
+        dst->err = "pic_state_to_fp64: the two contexts differ in configuration";
+        return PIC_EINVAL;
+    }
+    if (src->nb_slots > dst->cap_b || src->np_slots > dst->cap_p) {
+        dst->err = "pic_state_to_fp64: FP64 slot capacity too small: raise its options.max_steps";
+        return PIC_ENOMEM;
+    }
+    Ctx &d = *dst;
+    // fields: same ring layout once the window origin is copied
+    for (int k = 0; k < 3; ++k) {
+        hipLaunchKernelGGL(k_f2d, dim3(nblocks(B.nc, 256)), dim3(256), 0, d.st, (const float *)src->E32[k], d.E64[k],
+                           B.nc);
+        hipLaunchKernelGGL(k_f2d, dim3(nblocks(B.nc, 256)), dim3(256), 0, d.st, (const float *)src->B32[k], d.B64[k],
+                           B.nc);
+        PIC_HIP(d, hipMemsetAsync(d.J64[k], 0, 8 * (uint64_t)B.nc, d.st));
+    }
+    PIC_HIP(d, hipMemsetAsync(d.jion64, 0, 8 * (uint64_t)B.nz, d.st));
+    // particles to their slots; slots without a particle are dead
+    PIC_HIP(d, hipMemsetAsync(d.b64.alive, 0, 4 * (uint64_t)std::max<int64_t>(d.cap_b, 1), d.st));
+    PIC_HIP(d, hipMemsetAsync(d.p64.alive, 0, 4 * (uint64_t)std::max<int64_t>(d.cap_p, 1), d.st));
+    split_export64(*src, d.b64, d.p64, d.st);
+    d.step = src->step;
+    d.k0 = src->k0;
+    d.sh_lo = src->sh_lo;
+    d.sh_hi = src->sh_hi;
+    d.nb_slots = src->nb_slots;
+    d.np_slots = src->np_slots;
+    d.bw = src->bw;
+    PIC_HIP(d, hipStreamSynchronize(d.st));
+    return PIC_OK;
 }
 
 void pic_free(pic_ctx *c) {

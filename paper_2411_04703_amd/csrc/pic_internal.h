@@ -23,6 +23,7 @@ struct Part64 {
 struct Part32 {
     int32_t *cell;
     float *ox, *oy, *oz, *ux, *uy, *uz, *w;
+    int32_t *id;  // FP32 record mode: the particle's slot in the FP64 record layout (else null)
 };
 
 template <typename T> struct FieldsT {
@@ -119,13 +120,14 @@ int64_t compact64(Ctx &c, Part64 src, Part64 dst, int64_t n);  // returns surviv
 void split_setup(Ctx &c);
 bool split_tile_supported(int tx, int ty, int tz);  // tiles the FP32 step kernel is built for
 int split_lds_bytes(int tx, int ty, int tz);         // LDS of one FP32 step-kernel workgroup
-uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes);
+uint64_t split_state_payload(int64_t nc, int64_t slots_b, int64_t slots_p, uint64_t bins_bytes, int record);
+void split_export64(const Ctx &c, Part64 beam, Part64 plasma, hipStream_t st);  // record mode: particles to slots
 pic_status split_copy_state(Ctx &c, char *dev, bool save);  // snapshot <-> context (device buffer)
 void split_free(Ctx &c);
 void split_beam_init(Ctx &c, const double *normals_dev);
 pic_status split_plasma_fill(Ctx &c);  // also builds the initial bins of both species
 void split_step(Ctx &c, const StepCtx &S);
-void split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n);
+pic_status split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n);
 pic_status split_check(Ctx &c);  // bin capacity check + re-layout (synchronising)
 void split_read(Ctx &c, int species, double *dst7, int32_t *alive, int64_t *n);
 

@@ -143,6 +143,10 @@ class Sim:
     def set_state(self, buf: torch.Tensor):
         _check(self.L, self.ctx, self.L.pic_set_state(self.ctx, C.c_void_p(buf.data_ptr())), "pic_set_state")
 
+    def export_to(self, fp64: "Sim"):
+        """Write this FP32 record-mode state into an FP64 record-mode simulation of the same workload."""
+        _check(self.L, fp64.ctx, self.L.pic_state_to_fp64(self.ctx, fp64.ctx), "pic_state_to_fp64")
+
     def lambda_len(self) -> int:
         return int(self.L.pic_lambda_len(self.ctx))
 

@@ -39,10 +39,31 @@ def _case(name):
         w["plasma"].update(z_start_lab_m=g * (64 - 32 - 6) * dx, length_lab_m=g * 40 * dx, ramp_up_lab_m=g * 6 * dx)
         w["beam"]["charge_C"] = 3e-9
         return w
+    # degenerate cases of the method
+    if name == "plasma_only":  # no beam: the window speed is given
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=0)
+        w["frame"]["window_beta"] = 0.98
+        return w
+    if name == "beam_only":  # no plasma, no ions: most tiles empty
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=4096, sigma=(2, 2, 8))
+        w["plasma"]["n0_lab_cm3"] = 0.0
+        w["beam"]["charge_C"] = 3e-9
+        return w
+    if name == "static_window":  # window at rest: Mur at both faces, plasma still streaming through
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=4096, sigma=(2, 2, 8))
+        w["frame"]["window_beta"] = 0.0
+        w["beam"]["charge_C"] = 3e-9
+        return w
+    if name == "no_boost":  # gamma_R -> 1: the lab frame
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=4096, sigma=(2, 2, 8))
+        w["frame"]["gamma_boost"] = 1.0001
+        w["beam"]["charge_C"] = 3e-9
+        return w
     raise KeyError(name)
 
 
-CASES = ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "ramp_channel"]
+CASES = ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "ramp_channel", "plasma_only", "beam_only",
+         "static_window", "no_boost"]
 
 
 def _pair(w, seed=0, **opts):
