@@ -106,7 +106,7 @@ def copy_calibration(mib: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000, help="timed steps (default: the workload's full 1000-step run)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")

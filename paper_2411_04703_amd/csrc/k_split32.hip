@@ -31,9 +31,13 @@ constexpr int ST = 512;    // threads per workgroup of the auxiliary kernels
 constexpr int SST = 768;   // threads per workgroup of the step kernel (3 waves per SIMD)
 constexpr int CH = 6 * SST;  // particles per work item
 constexpr int WT = 512;    // threads of the work-list kernels
+constexpr int QPAD = 64;   // int32 stride of the slab queue counters: one 256-byte block each, apart from
+                           // everything else (a counter sharing a cache line with the read-only queue
+                           // bounds, or with another counter, slowed the step kernel by ~25 %)
 
 struct Store {
     Part32 buf[2];
+    int32_t *id[2];        // record mode: per-buffer particle ids (slots in the FP64 record layout), else null
     int64_t *off[2];       // nbins + 1 slot offsets of each buffer
     int32_t *cnt[2];       // per-buffer bin counts (may exceed the capacity: the excess is in the overflow tail)
     int32_t *ovf[2];       // per-buffer overflow counts
@@ -58,10 +62,11 @@ struct SplitState {
                  const float *);  // its instantiation (tile, deposit variant)
     int lds_bytes;
     SpeciesIO *ios;        // device descriptors: [cur 0][2], [cur 1][2], [flat init][2]
+    struct IdIO *iids;     // their record-mode id arrays, same order
     double *tabA;          // undulator phase table of the step, entry l + 1 for logical plane l (nz + 2)
     float *tabC, *tabS;
     int nslab;             // work queues: slabs of whole bin layers (one per XCD when they divide evenly)
-    int32_t *qnext, *qstart;  // per-slab item counters; slab q's items are [qstart[q], qstart[q + 1])
+    int32_t *qnext, *qstart;  // per-slab item counters (stride QPAD); slab q's items are [qstart[q], qstart[q + 1])
 };
 
 static SplitState &SS(Ctx &c) { return *static_cast<SplitState *>(c.split); }
@@ -126,14 +131,24 @@ struct SpeciesIO {
     OutStore out;
 };
 
-// both species' descriptors as one kernel argument
+// record mode: the id arrays of a species' input and output buffers
+struct IdIO {
+    const int32_t *in;
+    int32_t *out;
+};
+
+// both species' descriptors as one kernel argument; the ids come after both
+// SpeciesIO so that the descriptor fields the hot loop reads keep their
+// argument offsets (putting them inside made the step kernel ~25 % slower)
 struct IOPair {
     SpeciesIO s[2];
+    IdIO id[2];
 };
 
 // append (active lanes) to bin `bin` of the output store; overflow tail when the bin is full
+// (id_out: record mode, the particle id moves with it; null otherwise)
 __device__ inline void append(const OutStore &O, bool active, int bin, int cell, const float o[3], const float u[3],
-                              float w, int32_t *flags, int id) {
+                              float w, int32_t *flags, int32_t *id_out, int id) {
     int r = reserve_slot(active, active ? bin : 0, O.cnt);
     if (!active) return;
     int64_t b0 = gbl(O.off)[bin], cap = gbl(O.off)[bin + 1] - b0;
@@ -157,7 +172,7 @@ __device__ inline void append(const OutStore &O, bool active, int bin, int cell,
     gbl(b.uy)[s] = u[1];
     gbl(b.uz)[s] = u[2];
     gbl(b.w)[s] = w;
-    if (b.id) gbl(b.id)[s] = id;
+    if (id_out) gbl(id_out)[s] = id;
 }
 
 __device__ inline int bin_of(const Params &P, int i, int j, int l) {
@@ -190,12 +205,14 @@ __device__ inline int bin_count(const int64_t *off, const int32_t *cnt, int b) {
     return (int64_t)c < cap ? c : (int)cap;
 }
 
-// fixed-point value of one current contribution, rounded to nearest even: adding
-// 1.5 * 2^52 leaves the integer rint(v 2^f) in the low mantissa bits whenever
-// |v 2^f| < 2^51, which fixed_ok() has established for the whole particle
-__device__ inline long long to_fixed(float v, double fscale) {
+// fixed-point value rint(x y) of one current contribution, rounded to nearest
+// even: x y is the exact product of an FP32 factor and an FP32 factor scaled by
+// 2^f (at most 48 significant bits, so the FMA rounds once), and adding
+// 1.5 * 2^52 leaves the integer in the low mantissa bits whenever
+// |x y| < 2^51, which fixed_ok() has established for the whole particle
+__device__ inline long long to_fixed(double x, double y) {
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
-    return __double_as_longlong(fma((double)v, fscale, magic)) - __double_as_longlong(magic);
+    return __double_as_longlong(fma(x, y, magic)) - __double_as_longlong(magic);
 }
 
 // Every Esirkepov contribution of a particle is f P_c[m] A_c[a][b] with
@@ -212,7 +229,7 @@ struct PState {
     int id;  // record mode only
 };
 
-__device__ inline void load_particle(const Part32 &in, int64_t s, const Params &P, PState &q) {
+__device__ inline void load_particle(const Part32 &in, int64_t s, const Params &P, PState &q, const int32_t *id_in) {
     unpack_cell(P, gbl(in.cell)[s], q.i, q.j, q.l);
     q.o[0] = gbl(in.ox)[s];
     q.o[1] = gbl(in.oy)[s];
@@ -221,7 +238,7 @@ __device__ inline void load_particle(const Part32 &in, int64_t s, const Params &
     q.u[1] = gbl(in.uy)[s];
     q.u[2] = gbl(in.uz)[s];
     q.w = gbl(in.w)[s];
-    q.id = in.id ? gbl(in.id)[s] : 0;
+    q.id = id_in ? gbl(id_in)[s] : 0;
 }
 
 // undulator field at logical plane l: the plane's phase and envelope argument in
@@ -309,24 +326,33 @@ __device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
     }
 }
 
-// Esirkepov contributions: fn(c, r_along, r_a, r_b, value), r = node offsets from
-// the particle's cell along c and along the other two axes a, b in cyclic order.
+// Esirkepov contributions: fn(c, m, a, b, J) with J the 64-bit fixed-point
+// value of the contribution at node offsets base_c + m along c and base_a + a,
+// base_b + b along the other two axes a, b in cyclic order (m, a, b are
+// compile-time constants once the loops are unrolled, so the callers' LDS
+// addresses are one per-particle base plus an immediate offset).
 // Per component c the current factorises:
 //   J_c(m, a, b) = f P_c[m] A_c[a][b],  P_c[m] = sum_{m' <= m} DS_c[m'],
 //   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3),
 // and P_c[2] = -DS_c[3] (the DS sum to zero), exactly zero without a crossing.
+// The value converted is the exact product of the FP32 numbers f A_c[a][b]
+// and P_c[m] 2^fs.
 // DEP 0 visits nonzero contributions only (one branch each); DEP 1 visits all
 // 48 of a component that moves along its axis; DEP 2 leaves out the window's
 // last node along an axis (m = 2, a = 3 or b = 3) when no lane of the wave
 // crosses there (wave-uniform branches).  The values visited differ only by
 // zeros, so the integer current sums are the same.
-template <int C, int DEP, typename F> __device__ inline void esk_component(const Esk &e, float f, F &&fn) {
+template <int C, int DEP, typename F>
+__device__ inline void esk_component(const Esk &e, float f, double fscale, F &&fn) {
     constexpr int CA = C == 2 ? 0 : C + 1, CB = C == 0 ? 2 : C - 1;
     float Pm[3];
     Pm[0] = e.DS[C][0];
     Pm[1] = Pm[0] + e.DS[C][1];
     Pm[2] = -e.DS[C][3];
     if (DEP != 0 && Pm[0] == 0.0f && Pm[1] == 0.0f && Pm[2] == 0.0f) return;
+    double Pd[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Pd[m] = (double)Pm[m] * fscale;
     float ub[4], vb[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -344,12 +370,12 @@ template <int C, int DEP, typename F> __device__ inline void esk_component(const
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     if (b == 3 && !b3) break;
-                    const float fa = f * fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
+                    const double fa = (double)(f * fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]));
                     if (mm == 0) {
-                        fn(C, e.base[C], e.base[CA] + a, e.base[CB] + b, fa * Pm[0]);
-                        fn(C, e.base[C] + 1, e.base[CA] + a, e.base[CB] + b, fa * Pm[1]);
+                        fn(C, 0, a, b, to_fixed(fa, Pd[0]));
+                        fn(C, 1, a, b, to_fixed(fa, Pd[1]));
                     } else {
-                        fn(C, e.base[C] + 2, e.base[CA] + a, e.base[CB] + b, fa * Pm[2]);
+                        fn(C, 2, a, b, to_fixed(fa, Pd[2]));
                     }
                 }
             }
@@ -362,19 +388,19 @@ template <int C, int DEP, typename F> __device__ inline void esk_component(const
         for (int b = 0; b < 4; ++b) {
             float A = fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
             if (DEP == 0 && A == 0.0f) continue;
-            float fa = f * A;
+            const double fa = (double)(f * A);
 #pragma unroll
             for (int m = 0; m < 3; ++m)
-                if (DEP != 0 || Pm[m] != 0.0f) fn(C, e.base[C] + m, e.base[CA] + a, e.base[CB] + b, fa * Pm[m]);
+                if (DEP != 0 || Pm[m] != 0.0f) fn(C, m, a, b, to_fixed(fa, Pd[m]));
         }
 }
 
-template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, float f, F &&fn) {
-    esk_component<0, DEP>(e, f, fn);
+template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, float f, double fscale, F &&fn) {
+    esk_component<0, DEP>(e, f, fscale, fn);
     __builtin_amdgcn_sched_barrier(0);
-    esk_component<1, DEP>(e, f, fn);
+    esk_component<1, DEP>(e, f, fscale, fn);
     __builtin_amdgcn_sched_barrier(0);
-    esk_component<2, DEP>(e, f, fn);
+    esk_component<2, DEP>(e, f, fscale, fn);
 }
 
 // carry new offsets into the cell, apply the window shift; false if the particle left the band
@@ -530,13 +556,13 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
         atomicOr(flags, DFLAG_FIXED_OVERFLOW);
         return false;
     }
-    esk_visit<0>(e, fq, [&](int c, int ra, int rb, int rc, float v) {
+    esk_visit<0>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
+        const int ca = c == 2 ? 0 : c + 1, cb = c == 0 ? 2 : c - 1;
         int r[3];
-        r[c] = ra;
-        r[c == 2 ? 0 : c + 1] = rb;
-        r[c == 0 ? 2 : c - 1] = rc;
+        r[c] = e.base[c] + m;
+        r[ca] = e.base[ca] + a;
+        r[cb] = e.base[cb] + b;
         int p = ring_plane(q.l + r[2], S.k0r, P.nz);
-        long long iv = to_fixed(v, P.fscale);
         atomicAdd((unsigned long long *)&J[c][cell_index(P, q.i + r[0], q.j + r[1], p)], (unsigned long long)iv);
     });
     for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
@@ -570,15 +596,17 @@ template <class G> struct LdsBoxT {
     }
 };
 
-template <int TX, int TY, int TZ, int DEP>
+template <int TX, int TY, int TZ, int DEP, bool REC>
 __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, const int4 *items, const int32_t *qstart,
                                                       int32_t *qnext, int nslab, IOPair iop, FieldsT<float> f,
                                                       long long *Jx, long long *Jy, long long *Jz, int32_t *flags,
                                                       const double *gtabA, const float *gtabC, const float *gtabS) {
     using G = TileGeom<TX, TY, TZ>;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_item;
+    __shared__ int s_item, s_qstart[9];
     const int tid = threadIdx.x;
+    if (tid <= nslab) s_qstart[tid] = qstart[tid];  // constant during the launch
+    __syncthreads();
     float *Fs = (float *)smem;
     long long *Js = (long long *)(smem + G::EBYTES);
     double *tabA = (double *)(Js + G::NJ);
@@ -592,8 +620,8 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
         if (tid == 0) {
             int it = -1;
             while (hops < nslab) {
-                const int k = qstart[q] + atomicAdd(&qnext[q], 1);
-                if (k < qstart[q + 1]) {
+                const int k = s_qstart[q] + atomicAdd(&qnext[q * QPAD], 1);
+                if (k < s_qstart[q + 1]) {
                     it = k;
                     break;
                 }
@@ -661,7 +689,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
             bool act = base + tid < end;
             PState q;
             if (act) {
-                load_particle(IO.in, b0 + base + tid, P, q);
+                load_particle(IO.in, b0 + base + tid, P, q, REC ? iop.id[sp].in : nullptr);
                 const int li = q.i - t0x, lj = q.j - t0y, lk = q.l - t0z;
                 const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
                                     q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
@@ -684,17 +712,21 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                             atomicOr(flags, DFLAG_FIXED_OVERFLOW);
                             fq = 0.0f;
                         }
-                        // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2
-                        esk_visit<DEP>(e, fq, [&](int c, int ra, int rb, int rc, float v) {
-                            const long long iv = to_fixed(v, P.fscale);
-                            int idx;
-                            if (c == 0)  // (ra, rb, rc) = (x, y, z)
-                                idx = (li + ra + 2) + G::XX * ((lj + rb + 2) + G::XY * (lk + rc + 2));
+                        // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2;
+                        // one base index per component, the node offsets are immediates
+                        const int bx = li + e.base[0] + 2, by = lj + e.base[1] + 2, bz = lk + e.base[2] + 2;
+                        const int jb[3] = {bx + G::XX * (by + G::XY * bz),
+                                           G::NJX + bx + G::YX * (by + G::YY * bz),
+                                           G::NJX + G::NJY + bx + G::ZX * (by + G::ZY * bz)};
+                        esk_visit<DEP>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
+                            int off;
+                            if (c == 0)  // (m, a, b) along (x, y, z)
+                                off = m + G::XX * (a + G::XY * b);
                             else if (c == 1)  // (y, z, x)
-                                idx = G::NJX + (li + rc + 2) + G::YX * ((lj + ra + 2) + G::YY * (lk + rb + 2));
+                                off = b + G::YX * (m + G::YY * a);
                             else  // (z, x, y)
-                                idx = G::NJX + G::NJY + (li + rb + 2) + G::ZX * ((lj + rc + 2) + G::ZY * (lk + ra + 2));
-                            atomicAdd((unsigned long long *)&Js[idx], (unsigned long long)iv);
+                                off = a + G::ZX * (b + G::ZY * m);
+                            atomicAdd((unsigned long long *)&Js[jb[c] + off], (unsigned long long)iv);
                         });
                         for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
                         act = renormalise(P, S, q);
@@ -702,7 +734,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                 }
             }
             append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags, q.id);
+                   q.u, q.w, flags, REC ? iop.id[sp].out : nullptr, q.id);
         }
         __syncthreads();
         // flush nonzero LDS currents with global 64-bit integer atomics
@@ -748,21 +780,26 @@ using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int3
                             FieldsT<float>, long long *, long long *, long long *, int32_t *, const double *,
                             const float *, const float *);
 
-static StepKernel step_kernel(int tx, int ty, int tz, int dep) {
-#define PIC_PICK(a, b, c)                                                                            \
-    if (tx == a && ty == b && tz == c)                                                               \
-        return dep == 0 ? k_split_step<a, b, c, 0> : (dep == 1 ? k_split_step<a, b, c, 1> : k_split_step<a, b, c, 2>);
+// record mode has one instantiation per tile (the wave-pruned deposit: every
+// variant gives the same integer currents)
+static StepKernel step_kernel(int tx, int ty, int tz, int dep, bool rec) {
+#define PIC_PICK(a, b, c)                                                                              \
+    if (tx == a && ty == b && tz == c)                                                                 \
+        return rec ? k_split_step<a, b, c, 2, true>                                                    \
+                   : (dep == 0 ? k_split_step<a, b, c, 0, false>                                       \
+                               : (dep == 1 ? k_split_step<a, b, c, 1, false> : k_split_step<a, b, c, 2, false>));
     PIC_SPLIT_TILES(PIC_PICK)
 #undef PIC_PICK
     return nullptr;
 }
 
-bool split_tile_supported(int tx, int ty, int tz) { return step_kernel(tx, ty, tz, 0) != nullptr; }
+bool split_tile_supported(int tx, int ty, int tz) { return step_kernel(tx, ty, tz, 0, false) != nullptr; }
 
 // overflow tails of the previous step: untiled path, one particle per thread,
 // persistent grid over the tail lengths read on the device
-__global__ void __launch_bounds__(256) k_split_overflow(Params P, StepCtx S, const SpeciesIO *ios, FieldsT<float> f,
-                                                        long long *Jx, long long *Jy, long long *Jz, int32_t *flags) {
+__global__ void __launch_bounds__(256) k_split_overflow(Params P, StepCtx S, const SpeciesIO *ios, const IdIO *iids,
+                                                        FieldsT<float> f, long long *Jx, long long *Jy, long long *Jz,
+                                                        int32_t *flags) {
     const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
     for (int sp = 0; sp < 2; ++sp) {
         const SpeciesIO &IO = ios[sp];
@@ -772,18 +809,18 @@ __global__ void __launch_bounds__(256) k_split_overflow(Params P, StepCtx S, con
             bool act = k < n;
             PState q;
             if (act) {
-                load_particle(IO.in, IO.in_ovf_start + k, P, q);
+                load_particle(IO.in, IO.in_ovf_start + k, P, q, iids[sp].in);
                 act = particle_global(P, S, F6, Jx, Jy, Jz, q, flags);
             }
             append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags, q.id);
+                   q.u, q.w, flags, iids[sp].out, q.id);
         }
     }
 }
 
 // ---------------------------------------------------------------- rebin (no physics)
 __global__ void __launch_bounds__(ST) k_rebin(Params P, const int4 *items, const int32_t *nitems, int32_t *next,
-                                              const SpeciesIO *ios, int32_t *flags) {
+                                              const SpeciesIO *ios, const IdIO *iids, int32_t *flags) {
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int total = *nitems;
@@ -802,9 +839,9 @@ __global__ void __launch_bounds__(ST) k_rebin(Params P, const int4 *items, const
             int k = base + tid;
             bool act = k < end;
             PState q;
-            if (act) load_particle(IO.in, b0 + k, P, q);
+            if (act) load_particle(IO.in, b0 + k, P, q, iids[it.x].in);
             append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags, q.id);
+                   q.u, q.w, flags, iids[it.x].out, q.id);
         }
     }
 }
@@ -854,7 +891,7 @@ __global__ void k_wl_scan(int64_t *part, int nblk, const int32_t *ovf0, int64_t 
         part[b] = acc;
         acc += v;
     }
-    for (int q = 0; q < nslab; ++q) qnext[q] = 0;
+    for (int q = 0; q < nslab; ++q) qnext[q * QPAD] = 0;
     qstart[nslab] = (int32_t)min(acc, items_cap);  // the slab queues end before the overflow items
     int o0 = (int)min((int64_t)*ovf0, ocap0), o1 = (int)min((int64_t)*ovf1, ocap1);
     for (int k = 0; k < items_of(o0) && acc < items_cap; ++k) items[acc++] = make_int4(0, -1, k * CH, o0);
@@ -910,6 +947,11 @@ static void build_worklist(Ctx &c, int cur, int64_t in_cap0, int64_t in_cap1) {
                        X.nslab, X.scan_part, X.items, X.items_cap, b.cnt[o], p.cnt[o], X.qstart);
 }
 
+static IdIO species_ids(Ctx &c, int sp, int cur) {
+    Store &s = SS(c).s[sp];
+    return IdIO{s.id[cur], s.id[cur ^ 1]};
+}
+
 static SpeciesIO species_io(Ctx &c, int sp, int cur, int64_t in_ovf_start) {
     Store &s = SS(c).s[sp];
     int o = cur ^ 1;
@@ -933,10 +975,9 @@ static SpeciesIO species_io(Ctx &c, int sp, int cur, int64_t in_ovf_start) {
 // one particle buffer: 8 arrays of 4 B per slot, plus the id array in record mode
 static uint64_t slot_bytes(const Ctx &c) { return c.record ? 36 : 32; }
 
-static Part32 carve32(char *base, int64_t slots, bool ids) {
+static Part32 carve32(char *base, int64_t slots) {
     Part32 p;
     uint64_t n = (uint64_t)slots;
-    p.id = ids ? (int32_t *)(base + 32 * n) : nullptr;
     p.cell = (int32_t *)base;
     float *f = (float *)(base + 4 * n);
     p.ox = f;
@@ -961,8 +1002,11 @@ void split_setup(Ctx &c) {
         s.ovf_cap = sp ? c.ovf_cap_p : c.ovf_cap_b;
         int64_t slots = s.bin_slots + s.ovf_cap;
         char *b = A + (sp ? c.split_off_p : c.split_off_b);
-        s.buf[0] = carve32(b, slots, c.record);
-        s.buf[1] = carve32(b + slot_bytes(c) * (uint64_t)slots, slots, c.record);
+        for (int k = 0; k < 2; ++k) {
+            char *bk = b + k * slot_bytes(c) * (uint64_t)slots;
+            s.buf[k] = carve32(bk, slots);
+            s.id[k] = c.record ? (int32_t *)(bk + 32 * (uint64_t)slots) : nullptr;
+        }
     }
     char *bins = A + c.split_off_bins;
     int64_t *offs = (int64_t *)bins;
@@ -983,15 +1027,16 @@ void split_setup(Ctx &c) {
     X->tmpcnt = (int32_t *)(X->scan_part + nblocks(2 * nb, WT) + 8);
     X->tmpoff = (int64_t *)(X->tmpcnt + 2 * nb + 8);
     X->ios = (SpeciesIO *)(((uintptr_t)(X->tmpoff + nb + 8) + 15) & ~(uintptr_t)15);
-    X->tabA = (double *)(((uintptr_t)(X->ios + 6) + 15) & ~(uintptr_t)15);
+    X->iids = (IdIO *)(X->ios + 6);
+    X->tabA = (double *)(((uintptr_t)(X->iids + 6) + 15) & ~(uintptr_t)15);
     X->tabC = (float *)(X->tabA + P.nz + 2);
     X->tabS = X->tabC + P.nz + 2;
-    X->qnext = (int32_t *)(((uintptr_t)(X->tabS + P.nz + 2) + 15) & ~(uintptr_t)15);
-    X->qstart = X->qnext + 16;
+    X->qnext = (int32_t *)(((uintptr_t)(X->tabS + P.nz + 2) + 255) & ~(uintptr_t)255);
+    X->qstart = X->qnext + 8 * QPAD;  // its own 256-byte block
     X->nslab = P.ntz % 8 == 0 ? 8 : 1;  // workgroups are dispatched round-robin over the 8 XCDs
     X->lds_bytes = lds_bytes_of(P);
     // deposit: option 0 = wave-pruned windows, 1 = whole components, 2 = zero-skipping
-    X->kern = step_kernel(P.tx, P.ty, P.tz, c.opt.variant == 0 ? 2 : (c.opt.variant == 1 ? 1 : 0));
+    X->kern = step_kernel(P.tx, P.ty, P.tz, c.opt.variant == 0 ? 2 : (c.opt.variant == 1 ? 1 : 0), c.record != 0);
     const void *kern = (const void *)X->kern;
     (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, X->lds_bytes);
     // persistent grid: resident workgroups per CU as registers and LDS allow, or as requested
@@ -1010,6 +1055,9 @@ void split_setup(Ctx &c) {
                       species_io(c, 0, 1, X->s[0].bin_slots), species_io(c, 1, 1, X->s[1].bin_slots),
                       species_io(c, 0, 1, 0), species_io(c, 1, 1, 0)};
     (void)hipMemcpyAsync(X->ios, h, sizeof h, hipMemcpyHostToDevice, c.st);
+    IdIO hi[6] = {species_ids(c, 0, 0), species_ids(c, 1, 0), species_ids(c, 0, 1),
+                  species_ids(c, 1, 1), species_ids(c, 0, 1), species_ids(c, 1, 1)};
+    (void)hipMemcpyAsync(X->iids, hi, sizeof hi, hipMemcpyHostToDevice, c.st);
     (void)hipStreamSynchronize(c.st);
 }
 
@@ -1022,7 +1070,8 @@ void split_free(Ctx &c) {
 // beam: lab Gaussian -> boosted frame (FP64, as in the FP64 path) -> split
 // position, appended to a flat list at the start of buffer 1
 __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, double sy, double szl, double sux,
-                              double suy, double gB, double es, Part32 flat, int32_t *nflat, double *part) {
+                              double suy, double gB, double es, Part32 flat, int32_t *flat_id, int32_t *nflat,
+                              double *part) {
     __shared__ double red[2][ST];
     int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
     double cnt = 0.0, vzs = 0.0;
@@ -1076,7 +1125,7 @@ __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, d
         flat.uy[r] = s.u[1];
         flat.uz[r] = s.u[2];
         flat.w[r] = s.w;
-        if (flat.id) flat.id[r] = (int)q;  // beam slot = beam index
+        if (flat_id) flat_id[r] = (int)q;  // beam slot = beam index
     }
     red[0][threadIdx.x] = cnt;
     red[1][threadIdx.x] = vzs;
@@ -1097,7 +1146,7 @@ __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, d
 // plasma sheets [l0, l0 + nsheets) at time t, window origin k0: appended to bins
 // of `out` (bins == true) or to a flat list counted by out.ovf (bins == false)
 __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_t k0, OutStore out, int bins,
-                           int32_t *flags, int64_t id0) {
+                           int32_t *flags, int32_t *out_id, int64_t id0) {
     int64_t q = (int64_t)blockIdx.x * ST + threadIdx.x;
     bool act = q < total;
     PState s;
@@ -1129,7 +1178,7 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
         key = act ? bin_of(P, s.i, s.j, s.l) : 0;
     }
     if (bins) {
-        append(out, act, key, act ? pack_cell(P, s.i, s.j, s.l) : 0, s.o, s.u, s.w, flags, s.id);
+        append(out, act, key, act ? pack_cell(P, s.i, s.j, s.l) : 0, s.o, s.u, s.w, flags, out_id, s.id);
     } else {
         int r = reserve_slot(act, 0, out.ovf);
         if (act) {
@@ -1141,7 +1190,7 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
             out.buf.uy[r] = s.u[1];
             out.buf.uz[r] = s.u[2];
             out.buf.w[r] = s.w;
-            if (out.buf.id) out.buf.id[r] = s.id;
+            if (out_id) out_id[r] = s.id;
         }
     }
 }
@@ -1214,7 +1263,8 @@ static pic_status bins_from_flat(Ctx &c) {
     }
     // the flat lists are read as overflow tails that start at slot 0 and may fill the whole buffer
     build_worklist(c, 1, X.s[0].bin_slots + X.s[0].ovf_cap, X.s[1].bin_slots + X.s[1].ovf_cap);
-    hipLaunchKernelGGL(k_rebin, dim3(X.grid), dim3(ST), 0, c.st, P, X.items, X.nitems, X.next, X.ios + 4, c.dflags);
+    hipLaunchKernelGGL(k_rebin, dim3(X.grid), dim3(ST), 0, c.st, P, X.items, X.nitems, X.next, X.ios + 4, X.iids + 4,
+                       c.dflags);
     for (int sp = 0; sp < 2; ++sp) PIC_HIP(c, hipMemsetAsync(X.s[sp].ovf[1], 0, 4, c.st));
     c.cur32 = 0;
     PIC_HIP(c, hipStreamSynchronize(c.st));
@@ -1232,7 +1282,7 @@ void split_beam_init(Ctx &c, const double *normals_dev) {
     hipLaunchKernelGGL(k_beam_init32, dim3(nblk), dim3(ST), 0, c.st, P, normals_dev, n, c.beam.sigma_cells[0],
                        c.beam.sigma_cells[1], c.beam.sigma_cells[2] / F, c.beam.emit_n_m[0] / (c.beam.sigma_cells[0] * D),
                        c.beam.emit_n_m[1] / (c.beam.sigma_cells[1] * D), c.beam.gamma_lab, c.beam.rel_energy_spread_rms,
-                       X.s[0].buf[1], X.s[0].ovf[1], c.red);
+                       X.s[0].buf[1], X.s[0].id[1], X.s[0].ovf[1], c.red);
     std::vector<double> h(2 * (size_t)nblk);
     (void)hipMemcpyAsync(h.data(), c.red, 16 * (uint64_t)nblk, hipMemcpyDeviceToHost, c.st);
     (void)hipStreamSynchronize(c.st);
@@ -1247,7 +1297,8 @@ void split_beam_init(Ctx &c, const double *normals_dev) {
 // inject the nonzero-weight sheets of [l0, l1) at time t: one launch per run of
 // consecutive nonzero-weight sheets, whose particles take the next ids (the
 // slots the FP64 record layout gives them, in the same order)
-static pic_status inject_runs32(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0, const OutStore &o, int bins) {
+static pic_status inject_runs32(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0, const OutStore &o,
+                                int32_t *o_id, int bins) {
     const Params &P = c.P;
     const int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
     int64_t l = l0;
@@ -1262,7 +1313,7 @@ static pic_status inject_runs32(Ctx &c, int64_t l0, int64_t l1, double t, int64_
                 return PIC_ERANGE;
             }
             hipLaunchKernelGGL(k_inject32, dim3(nblocks(total, ST)), dim3(ST), 0, c.st, P, a, total, t, k0, o, bins,
-                               c.dflags, c.np_slots);
+                               c.dflags, o_id, c.np_slots);
             c.np_slots += total;
         }
     }
@@ -1280,7 +1331,7 @@ pic_status split_plasma_fill(Ctx &c) {
         o.ovf = X.s[1].ovf[1];
         o.bin_slots = X.s[1].bin_slots;
         o.ovf_cap = X.s[1].ovf_cap;
-        pic_status st = inject_runs32(c, c.sh_lo, c.sh_hi, 0.0, 0, o, 0);
+        pic_status st = inject_runs32(c, c.sh_lo, c.sh_hi, 0.0, 0, o, X.s[1].id[1], 0);
         if (st != PIC_OK) return st;
     }
     return bins_from_flat(c);
@@ -1306,9 +1357,12 @@ void split_step(Ctx &c, const StepCtx &S) {
     timing_end(c, 2, t1);
     hipEvent_t t2 = timing_begin(c);
     hipLaunchKernelGGL(X.kern, dim3(X.grid), dim3(SST), X.lds_bytes, c.st, P, S, X.items, X.qstart, X.qnext, X.nslab,
-                       IOPair{{species_io(c, 0, cur, X.s[0].bin_slots), species_io(c, 1, cur, X.s[1].bin_slots)}}, f,
+                       IOPair{{species_io(c, 0, cur, X.s[0].bin_slots), species_io(c, 1, cur, X.s[1].bin_slots)},
+                              {species_ids(c, 0, cur), species_ids(c, 1, cur)}},
+                       f,
                        c.Ji[0], c.Ji[1], c.Ji[2], c.dflags, X.tabA, X.tabC, X.tabS);
-    hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, f, c.Ji[0], c.Ji[1],
+    hipLaunchKernelGGL(k_split_overflow, dim3(256), dim3(256), 0, c.st, P, S, X.ios + 2 * cur, X.iids + 2 * cur, f,
+                       c.Ji[0], c.Ji[1],
                        c.Ji[2], c.dflags);
     timing_end(c, 0, t2);
     hipEvent_t t3 = timing_begin(c);
@@ -1335,7 +1389,7 @@ pic_status split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64
         out.ovf = X.s[1].ovf[o];
         out.bin_slots = X.s[1].bin_slots;
         out.ovf_cap = X.s[1].ovf_cap;
-        pic_status st = inject_runs32(c, l0, l1, t, k0n, out, 1);
+        pic_status st = inject_runs32(c, l0, l1, t, k0n, out, X.s[1].id[o], 1);
         if (st != PIC_OK) return st;
     }
     c.cur32 = o;
@@ -1346,8 +1400,8 @@ pic_status split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64
 // every particle of the current buffer to its FP64 record slot (its id):
 // absolute boosted position, momentum, weight, alive; one block per bin, the
 // last block takes the overflow tail
-__global__ void k_split_export(Params P, int64_t k0, Part32 in, const int64_t *off, const int32_t *cnt,
-                               int64_t ovf_start, const int32_t *ovf, int64_t ovf_cap, Part64 dst) {
+__global__ void k_split_export(Params P, int64_t k0, Part32 in, const int32_t *in_id, const int64_t *off,
+                               const int32_t *cnt, int64_t ovf_start, const int32_t *ovf, int64_t ovf_cap, Part64 dst) {
     const int b = blockIdx.x;
     int64_t s0, n;
     if (b < P.nbins) {
@@ -1358,7 +1412,7 @@ __global__ void k_split_export(Params P, int64_t k0, Part32 in, const int64_t *o
         n = min((int64_t)*ovf, ovf_cap);
     }
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
-        const int64_t s = s0 + k, d = in.id[s];
+        const int64_t s = s0 + k, d = in_id[s];
         int i, j, l;
         unpack_cell(P, in.cell[s], i, j, l);
         dst.x[d] = i + (double)in.ox[s];
@@ -1377,7 +1431,8 @@ void split_export64(const Ctx &c, Part64 beam, Part64 plasma, hipStream_t st) {
     for (int sp = 0; sp < 2; ++sp) {
         const Store &S = X.s[sp];
         hipLaunchKernelGGL(k_split_export, dim3(c.P.nbins + 1), dim3(256), 0, st, c.P, c.k0, S.buf[c.cur32],
-                           S.off[c.cur32], S.cnt[c.cur32], S.bin_slots, S.ovf[c.cur32], S.ovf_cap, sp ? plasma : beam);
+                           S.id[c.cur32], S.off[c.cur32], S.cnt[c.cur32], S.bin_slots, S.ovf[c.cur32], S.ovf_cap,
+                           sp ? plasma : beam);
     }
 }
 
@@ -1478,7 +1533,7 @@ pic_status split_check(Ctx &c) {
     }
     build_worklist(c, cur, X.s[0].ovf_cap, X.s[1].ovf_cap);
     hipLaunchKernelGGL(k_rebin, dim3(X.grid), dim3(ST), 0, c.st, P, X.items, X.nitems, X.next, X.ios + 2 * cur,
-                       c.dflags);
+                       X.iids + 2 * cur, c.dflags);
     for (int sp = 0; sp < 2; ++sp) {
         pic_status s = upload_layout(c, sp, lay[sp], cur);
         if (s != PIC_OK) return s;

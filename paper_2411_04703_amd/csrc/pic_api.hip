@@ -239,7 +239,7 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
         off[13] = take(bins_bytes);
         int64_t items_cap = (cb + cp + pl.ovf_b + pl.ovf_p) / 4096 + 2 * nbins + 64;
         uint64_t wl_bytes = 16 * (uint64_t)(P.nz + 8) + 256 + 16 * (uint64_t)items_cap + 8 * (uint64_t)((2 * nbins) / 512 + 16) +
-                            4 * (uint64_t)(2 * nbins + 8) + 8 * (uint64_t)(nbins + 8) + 4096;
+                            4 * (uint64_t)(2 * nbins + 8) + 8 * (uint64_t)(nbins + 8) + 4096 + 4096;
         off[14] = take(wl_bytes);
         off[20] = cb;  // slot capacities (not offsets)
         off[21] = cp;

@@ -23,7 +23,6 @@ struct Part64 {
 struct Part32 {
     int32_t *cell;
     float *ox, *oy, *oz, *ux, *uy, *uz, *w;
-    int32_t *id;  // FP32 record mode: the particle's slot in the FP64 record layout (else null)
 };
 
 template <typename T> struct FieldsT {
