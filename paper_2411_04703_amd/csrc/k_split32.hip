@@ -1212,12 +1212,14 @@ static bool layout_from_counts(Ctx &c, int sp, const std::vector<int32_t> &cnt, 
     for (int64_t b = 0; b < nb; ++b) total += cnt[b];
     int64_t spare = s.bin_slots - total;
     if (spare < 0) return false;
-    // every bin: count + 1/8 of its count + an even share of the remaining room
+    // every bin: count + headroom (1/2 of its count for the beam, which pinches and drifts between
+    // re-layouts; 1/8 for the plasma) + an even share of the remaining room
+    const int64_t hd = sp == 0 ? 2 : 8;
     int64_t extra = 0;
-    for (int64_t b = 0; b < nb; ++b) extra += cnt[b] / 8;
+    for (int64_t b = 0; b < nb; ++b) extra += cnt[b] / hd;
     int64_t share = std::max<int64_t>(0, (spare - extra) / std::max<int64_t>(1, nb));
     for (int64_t b = 0; b < nb; ++b) {
-        int64_t cap = cnt[b] + (extra <= spare ? cnt[b] / 8 : 0) + share;
+        int64_t cap = cnt[b] + (extra <= spare ? cnt[b] / hd : 0) + share;
         off[b + 1] = off[b] + cap;
     }
     return off[nb] <= s.bin_slots;

@@ -227,10 +227,13 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
         off[10] = take(4 * 8 * (uint64_t)P.plane);
         // particle double buffers with bin slack and an overflow tail (k_split32.hip)
         int64_t nbins = P.nbins;
-        int64_t cb = pl.cap_b + pl.cap_b / 4 + 32 * nbins + 4096;
+        // bin slack: the beam pinches and moves between re-layouts, so its bins get 1/2 of their count as
+        // headroom and an overflow tail as large as the beam (it can never lose particles); the plasma
+        // gets 1/8 and a tail of 1/8 of its lattice
+        int64_t cb = pl.cap_b + pl.cap_b / 2 + 32 * nbins + 4096;
         int64_t cp = pl.cap_p + pl.cap_p / 4 + 32 * nbins + 4096;
-        pl.ovf_b = std::max<int64_t>(8192, pl.cap_b / 16);
-        pl.ovf_p = std::max<int64_t>(8192, pl.cap_p / 16);
+        pl.ovf_b = std::max<int64_t>(8192, pl.cap_b);
+        pl.ovf_p = std::max<int64_t>(8192, pl.cap_p / 8);
         pl.cap_b = b->n_macro;
         const uint64_t sb = pl.record ? 36 : 32;  // record mode: + the particle id
         off[11] = take(sb * (uint64_t)(cb + pl.ovf_b) * 2);
