@@ -134,3 +134,37 @@ def test_workload1_fp32_tracks_fp64_at_full_size():
     for f in FIELDS:
         err = np.linalg.norm(a.field(f) - b.field(f))
         assert err <= 1e-4 * max(total, gross), (f, err, total, gross)
+
+
+def test_workload1_full_run_fp32_within_stated_tolerance():
+    """After the workload's full 1000 steps the FP32 path's beam moments and
+    bunching factor agree with the FP64 path's (which follows the oracle to
+    1e-12 per step at small sizes) within the stated tolerance: per quantity,
+    max(1e-3 relative, 3x the spread between two FP64 runs whose initial beam
+    positions differ by one FP32 rounding); the bunching factor, which is at
+    noise level here, absolutely within max(1e-6, 3x that spread)."""
+    from paper_2411_04703_amd.sim import Sim
+    nsteps = W["steps"]
+    nrm = pin.beam_normals(W["beam"]["n_macro"], 0)
+    nrm_p = nrm.copy()
+    nrm_p[:3] *= 1.0 + 2.0 ** -24  # x, y, z draws: one FP32 rounding of the initial positions
+    out = []
+    for prec, g in ((1, nrm), (0, nrm), (0, nrm_p)):
+        s = Sim(W, g, precision=prec, **({} if prec else {"max_steps": 64}))
+        s.step(nsteps)
+        out.append(s.diag())
+        del s
+    d32, d64, d64p = out
+    assert d32["n_beam"] == d64["n_beam"] and d32["n_plasma"] == d64["n_plasma"]
+    report = {}
+    for k in ("mean", "sigma", "usigma", "emit"):
+        a, b, c = (np.asarray(d[k], dtype=float) for d in (d32, d64, d64p))
+        scale = np.maximum(np.abs(b), 1e-300)
+        err, spread = np.abs(a - b) / scale, np.abs(c - b) / scale
+        tol = np.maximum(1e-3, 3.0 * spread)
+        report[k] = (err.tolist(), tol.tolist())
+        assert np.all(err <= tol), (k, err, tol)
+    eb, sb = abs(d32["b1_abs"] - d64["b1_abs"]), abs(d64p["b1_abs"] - d64["b1_abs"])
+    report["b1_abs"] = (eb, max(1e-6, 3.0 * sb))
+    print("full-run tolerance report", report)
+    assert eb <= max(1e-6, 3.0 * sb), report
