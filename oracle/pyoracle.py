@@ -272,3 +272,78 @@ def push(pusher: int, qm: float, dt: float, u, E, B):
     out = np.zeros(3)
     L.orc_push(pusher, qm, dt, u.ctypes.data, E.ctypes.data, B.ctypes.data, out.ctypes.data)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Initial self-field of the beam (boosted frame, t' = 0).
+#
+# Section 1 transforms fields between frames.  The beam moves along z at
+# beta_b in the boosted frame; in its own rest frame its field is
+# electrostatic, E_r = -grad phi_r with lap phi_r = -rho_r.  Transforming with
+# z_r = gamma_b z', rho' = gamma_b rho_r, phi' = gamma_b phi_r gives, on the
+# boosted grid,
+#     (d_xx + d_yy + d_zz / gamma_b^2) phi' = -rho',
+#     E'_perp = -grad_perp phi',  E'_z = -d_z phi' / gamma_b^2,  B' = beta_b z x E'.
+# Discretisation (the Yee grid of the step): phi and rho on nodes, E on edges,
+# B on faces; second differences D+D-; periodic in x and y like the field
+# solver, phi = 0 one plane beyond each z face.  Then div E = rho holds node
+# by node.  The state between steps is (E^n, B^(n-1/2)): the pattern moves at
+# beta_b, so B is taken at t' = -dt/2, i.e. beta_b z x E displaced by
+# beta_b dt / 2 along z (linear interpolation between the planes).
+def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: float):
+    """phi, (Ex, Ey, Ez), (Bx, By, Bz) for node charge rho of shape (nz, ny, nx).
+
+    The transverse operator is diagonalised with a 2D FFT (library primitive);
+    each (kx, ky) column is then a tridiagonal system in z, solved by plain
+    forward elimination and back substitution."""
+    rho = np.asarray(rho, dtype=np.float64)
+    nz, ny, nx = rho.shape
+    g2 = 1.0 / (gamma_b * gamma_b)
+    R = np.fft.fft2(rho, axes=(1, 2))
+    lam = (-4.0 * np.sin(np.pi * np.arange(ny) / ny) ** 2)[:, None] + \
+          (-4.0 * np.sin(np.pi * np.arange(nx) / nx) ** 2)[None, :]
+    # rows: g2 phi[l-1] + (lam - 2 g2) phi[l] + g2 phi[l+1] = -R[l], phi[-1] = phi[nz] = 0
+    diag = lam - 2.0 * g2
+    cp = np.empty((nz, ny, nx))
+    dp = np.empty((nz, ny, nx), dtype=complex)
+    cp[0] = g2 / diag
+    dp[0] = -R[0] / diag
+    for l in range(1, nz):
+        m = diag - g2 * cp[l - 1]
+        cp[l] = g2 / m
+        dp[l] = (-R[l] - g2 * dp[l - 1]) / m
+    ph = np.empty_like(dp)
+    ph[nz - 1] = dp[nz - 1]
+    for l in range(nz - 2, -1, -1):
+        ph[l] = dp[l] - cp[l] * ph[l + 1]
+    phi = np.real(np.fft.ifft2(ph, axes=(1, 2)))
+    up = np.concatenate([phi[1:], np.zeros((1, ny, nx))], axis=0)  # phi one plane up (0 beyond the top)
+    Ex = -(np.roll(phi, -1, axis=2) - phi)
+    Ey = -(np.roll(phi, -1, axis=1) - phi)
+    Ez = -(up - phi) * g2
+    w = 0.5 + 0.5 * beta_b * dt  # weight of the upper plane at z = l + 1/2 + beta_b dt / 2
+    zero = np.zeros((1, ny, nx))
+    Exu = np.concatenate([Ex[1:], zero], axis=0)
+    Eyu = np.concatenate([Ey[1:], zero], axis=0)
+    Bx = -beta_b * ((1.0 - w) * Ey + w * Eyu)
+    By = beta_b * ((1.0 - w) * Ex + w * Exu)
+    Bz = np.zeros_like(phi)
+    return phi, (Ex, Ey, Ez), (Bx, By, Bz)
+
+
+def beam_mean_beta(sim: "Sim") -> float:
+    """Mean boosted beta_z of the live beam particles (equal weights)."""
+    p = sim.particles(0)
+    al = p["alive"] == 1
+    ux, uy, uz = (np.real(p[k][al]) for k in ("ux", "uy", "uz"))
+    return float(np.mean(uz / np.sqrt(1.0 + ux * ux + uy * uy + uz * uz)))
+
+
+def init_beam_fields(sim: "Sim"):
+    """Overwrite the simulation's (zero) initial fields with the beam's self-field."""
+    beta = beam_mean_beta(sim)
+    gamma = 1.0 / np.sqrt((1.0 - beta) * (1.0 + beta))
+    _, E, B = relativistic_poisson(np.real(sim.rho(1)), gamma, beta, sim.info().dt)
+    for name, v in zip(FIELD_NAMES, E + B):
+        sim.field(name)[:] = v
+    return beta, gamma

@@ -1,0 +1,127 @@
+"""Pins of the oracle's initial beam self-field (the relativistic Poisson
+problem of the boosted frame, section 1 field transformation).
+
+* brute force: the FFT + tridiagonal solver equals a dense linear solve of the
+  same discrete operator, written out node by node, on a tiny grid;
+* Gauss: the oracle's own divergence (C code) of the field equals the charge;
+* closed form: far from a point charge moving at beta, the field is the
+  relativistic Coulomb field, gamma q / (4 pi r^2) across the motion and
+  q / (4 pi gamma^2 r^2) along it (gamma^3 between the two);
+* quasi-statics: one Yee step of the oracle from this field moves the pattern
+  with the beam, so E after one step equals the initial field of the moved
+  beam (a wrong sign or time level of B would launch a transient instead).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import picinputs as pin
+from oracle import pyoracle as po
+
+pytestmark = pytest.mark.usefixtures("oracle_built")
+
+
+def _dense_solve(rho, g2):
+    """(D_xx + D_yy + g2 D_zz) phi = -rho, periodic x, y, phi = 0 beyond the z faces: one row per node."""
+    nz, ny, nx = rho.shape
+    n = rho.size
+    A = np.zeros((n, n))
+
+    def idx(i, j, l):
+        return (l * ny + j % ny) * nx + i % nx
+
+    for l in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = idx(i, j, l)
+                A[r, idx(i + 1, j, l)] += 1.0
+                A[r, idx(i - 1, j, l)] += 1.0
+                A[r, idx(i, j + 1, l)] += 1.0
+                A[r, idx(i, j - 1, l)] += 1.0
+                A[r, r] -= 4.0 + 2.0 * g2
+                if l + 1 < nz:
+                    A[r, idx(i, j, l + 1)] += g2
+                if l > 0:
+                    A[r, idx(i, j, l - 1)] += g2
+    return np.linalg.solve(A, -rho.ravel()).reshape(rho.shape)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 3.7])
+def test_poisson_equals_dense_solve(gamma):
+    rng = np.random.default_rng(5)
+    rho = rng.standard_normal((7, 5, 6))
+    beta = math.sqrt(1.0 - 1.0 / gamma**2)
+    phi, _, _ = po.relativistic_poisson(rho, gamma, beta, 0.5)
+    ref = _dense_solve(rho, 1.0 / gamma**2)
+    assert np.abs(phi - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _beam_only(nx=32, ny=32, nz=64, n=4096, sigma=(2, 2, 6)):
+    w = pin.scaled(pin.workload(1), nx=nx, ny=ny, nz=nz, n_beam=n, sigma=sigma)
+    w["plasma"]["n0_lab_cm3"] = 0.0
+    w["plasma"]["ions"] = 0
+    w["beam"]["charge_C"] = 3e-9
+    return w
+
+
+def test_initial_field_satisfies_gauss_law():
+    w = _beam_only()
+    s = po.Sim(w, pin.beam_normals(w["beam"]["n_macro"], 1))
+    beta, gamma = po.init_beam_fields(s)
+    assert 0.9 < beta < 1.0 and gamma > 2.0
+    r = s.gauss()[1:]  # the oracle's divergence leaves out E_z below plane 0
+    rho = s.rho(1)
+    assert np.abs(rho).max() > 0
+    assert np.abs(r).max() <= 1e-12 * np.abs(rho).max()
+    # the field is not trivial: transverse and longitudinal parts of the expected size
+    assert np.abs(s.field("Ex")).max() > 1e-3 * np.abs(rho).max()
+
+
+def test_point_charge_far_field_is_relativistic_coulomb():
+    nx = ny = 192
+    nz = 128
+    gamma = 2.0
+    beta = math.sqrt(1.0 - 1.0 / gamma**2)
+    rho = np.zeros((nz, ny, nx))
+    c0 = (nz // 2, ny // 2, nx // 2)
+    s1 = {-1: 0.125, 0: 0.75, 1: 0.125}  # quadratic shape of a charge sitting on a node
+    for a, wa in s1.items():
+        for b, wb in s1.items():
+            for c, wc in s1.items():
+                rho[c0[0] + c, c0[1] + b, c0[2] + a] = wa * wb * wc
+    _, (Ex, Ey, Ez), _ = po.relativistic_poisson(rho, gamma, beta, 0.5)
+    # at 7-9 cells the grid (a few % at r ~ 5, falling as 1/r^2), the periodic transverse images and
+    # the zero-potential z faces each shift the field by about 1 %; a missing or extra factor of gamma
+    # would be off by 100 % or more
+    for d in (7, 9):
+        r = d + 0.5  # E_x[i] sits at x = i + 1/2, E_z[l] at z = l + 1/2
+        ex = Ex[c0[0], c0[1], c0[2] + d]
+        ez = Ez[c0[0] + d, c0[1], c0[2]]
+        assert ex == pytest.approx(gamma / (4 * math.pi * r * r), rel=0.04), d
+        assert ez == pytest.approx(1.0 / (4 * math.pi * gamma**2 * r * r), rel=0.04), d
+        assert ex / ez == pytest.approx(gamma**3, rel=0.04), d
+
+
+def test_initial_field_moves_with_the_beam():
+    """E and B after one oracle step from the initial field = initial field of
+    the moved beam.  The residual is the grid-scale part of a grainy charge
+    density moving 0.54 cells (it falls as the particle count grows); leaving
+    B out, or flipping its sign, gives errors of 100-200 % in B and E_z."""
+    w = _beam_only(n=65536, sigma=(3, 3, 8))
+    w["beam"]["charge_C"] = 3e-12  # self-fields must not change the orbits over the step
+    w["beam"]["rel_energy_spread_rms"] = 0.0
+    w["beam"]["emit_n_m"] = [1e-9, 1e-9]
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 2)
+    a = po.Sim(w, nrm)
+    po.init_beam_fields(a)
+    a.step(1)
+    b = po.Sim(w, nrm)
+    b.step(1)
+    assert np.abs(a.particles(0)["z"] - b.particles(0)["z"]).max() < 1e-6
+    po.init_beam_fields(b)  # E^1 and B^(1/2) of the moved beam
+    for f, tol in (("Ex", 0.04), ("Ey", 0.04), ("Ez", 0.1), ("Bx", 0.03), ("By", 0.03)):
+        ea, eb = a.field(f), b.field(f)
+        scale = np.abs(eb).max()
+        assert scale > 0
+        assert np.abs(ea - eb).max() <= tol * scale, (f, np.abs(ea - eb).max() / scale)
