@@ -136,6 +136,14 @@ typedef struct {
  *          contributions only, one branch each.  All give identical results.
  * wg_per_cu: resident workgroups per compute unit of the FP32 particle kernel's
  *            persistent grid; 0 = as many as registers and LDS allow.
+ * init_fields: 0 = E = B = 0 at t' = 0 (a frozen neutralising background);
+ *              1 = the beam's self-field: its rest-frame electrostatic field
+ *              carried into the boosted frame (section 1 field
+ *              transformation), i.e. (d_xx + d_yy + d_zz / gamma_b^2) phi =
+ *              -rho solved in FP64 on the grid (periodic x, y; phi = 0 beyond
+ *              the z faces; gamma_b from the beam's mean boosted beta_z),
+ *              E = -(d_x, d_y, d_z / gamma_b^2) phi, B = beta_b z x E at
+ *              t' = -dt/2.  Transverse grid edges up to 2048.
  * stream: hipStream_t for all launches (NULL: null stream). */
 typedef struct {
     int32_t precision, pusher;
@@ -143,7 +151,7 @@ typedef struct {
     int32_t fixed_point_frac_bits, check_every;
     int32_t tile[3], max_steps;
     int32_t record, variant;
-    int32_t wg_per_cu, reserved;
+    int32_t wg_per_cu, init_fields;
     void *stream;
 } pic_options;
 

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpicrrf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["pic_api.hip", "k_fdtd.hip", "k_plain64.hip", "k_split32.hip", "k_diag.hip", "k_adjoint.hip"]
+SOURCES = ["pic_api.hip", "k_fdtd.hip", "k_plain64.hip", "k_split32.hip", "k_diag.hip", "k_adjoint.hip",
+           "k_initfield.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -18,7 +18,7 @@
 
 namespace pic {
 
-void split_rho(Ctx &c, double *rho);                 // k_split32.hip
+void split_rho(Ctx &c, double *rho, int mask);       // k_split32.hip
 void split_plasma_kinetic(Ctx &c, double *out2);     // k_split32.hip
 int64_t split_beam_to64(Ctx &c, double *dst6);       // k_split32.hip
 
@@ -216,6 +216,18 @@ static void host_sum(Ctx &c, int nblk, int nv, std::vector<double> &acc) {
         for (int k = 0; k < nv; ++k) acc[k] += h[(size_t)b * nv + k];
 }
 
+// beam charge on the nodes (ring order), added into rho
+void beam_rho(Ctx &c, double *rho) {
+    const Params &P = c.P;
+    if (c.precision == PIC_FP64_PLAIN) {
+        if (c.nb_slots)
+            hipLaunchKernelGGL(k_rho64, dim3(nblocks(c.nb_slots, DT)), dim3(DT), 0, c.st, P, c.k0,
+                               (int)(c.k0 % P.nz), c.b64, c.nb_slots, rho);
+    } else {
+        split_rho(c, rho, 1);
+    }
+}
+
 pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
     memset(o, 0, sizeof *o);
     const Params &P = c.P;
@@ -333,7 +345,7 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
             if (c.nb_slots) hipLaunchKernelGGL(k_rho64, dim3(nblocks(c.nb_slots, DT)), dim3(DT), 0, c.st, P, c.k0, k0r, c.b64, c.nb_slots, rho);
             if (c.np_slots) hipLaunchKernelGGL(k_rho64, dim3(nblocks(c.np_slots, DT)), dim3(DT), 0, c.st, P, c.k0, k0r, c.p64, c.np_slots, rho);
         } else {
-            split_rho(c, rho);
+            split_rho(c, rho, 3);
         }
         if (P.ions && c.sh_hi > c.sh_lo)
             hipLaunchKernelGGL(k_rho_ion, dim3(nblocks(c.sh_hi - c.sh_lo, 128)), dim3(128), 0, c.st, P, c.sh_lo,

@@ -1693,10 +1693,11 @@ int64_t split_beam_to64(Ctx &c, double *dst6) {
     return tot;
 }
 
-void split_rho(Ctx &c, double *rho) {
+void split_rho(Ctx &c, double *rho, int mask) {
     SplitState &X = SS(c);
     int cur = c.cur32;
     for (int sp = 0; sp < 2; ++sp) {
+        if (!(mask & (1 << sp))) continue;
         Store &s = X.s[sp];
         int32_t ovf_n = 0;
         (void)hipMemcpyAsync(&ovf_n, s.ovf[cur], 4, hipMemcpyDeviceToHost, c.st);

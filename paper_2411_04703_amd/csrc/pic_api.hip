@@ -68,6 +68,9 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (o->pusher < -1 || o->pusher > 1) return fail(err, PIC_EINVAL, "options: pusher");
     if (o->variant < 0 || o->variant > 2) return fail(err, PIC_EINVAL, "options: variant 0, 1 or 2");
     if (o->wg_per_cu < 0 || o->wg_per_cu > 8) return fail(err, PIC_EINVAL, "options: wg_per_cu in [0, 8]");
+    if (o->init_fields != 0 && o->init_fields != 1) return fail(err, PIC_EINVAL, "options: init_fields is 0 or 1");
+    if (o->init_fields && (g->nx > 2048 || g->ny > 2048))
+        return fail(err, PIC_EINVAL, "options: init_fields needs transverse grid edges <= 2048");
 
     memset(&P, 0, sizeof P);
     memset(&d, 0, sizeof d);
@@ -555,6 +558,7 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
             }
             bw = cnt > 0 ? vz / cnt : 0.0;
         }
+        c->beam_beta0 = bw;
     } else {
         c->split_slots_b = (int64_t)off[20];
         c->split_slots_p = (int64_t)off[21];
@@ -570,6 +574,7 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
         c->np_slots = 0;
         split_setup(*c);
         if (b->n_macro > 0) split_beam_init(*c, c->stage);
+        c->beam_beta0 = c->bw;
     }
     c->bw = f->window_beta >= 0 ? f->window_beta : (pl.precision == PIC_FP64_PLAIN ? bw : c->bw);
     // plasma lattice at t' = 0 inside the active band
@@ -582,6 +587,7 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
     } else {
         s = split_plasma_fill(*c);
     }
+    if (s == PIC_OK && o->init_fields && b->n_macro > 0) s = init_beam_fields(*c);
     if (s != PIC_OK) {
         fprintf(stderr, "pic_init: %s\n", c->err.c_str());
         if (c->split) split_free(*c);

@@ -42,6 +42,7 @@ struct Ctx {
     pic_undulator und;
     pic_options opt;
     double bw = 0, k_bunch_default = 0;
+    double beam_beta0 = 0;  // mean boosted beta_z of the beam at t' = 0
 
     // host-side dynamic state (deterministic, no device read needed)
     int64_t step = 0, k0 = 0, sh_lo = 0, sh_hi = 0;
@@ -132,6 +133,10 @@ void split_read(Ctx &c, int species, double *dst7, int32_t *alive, int64_t *n);
 
 // diagnostics (k_diag.hip)
 pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *out);
+void beam_rho(Ctx &c, double *rho);  // beam charge on the nodes (ring order), added into rho
+
+// initial beam self-field (k_initfield.hip)
+pic_status init_beam_fields(Ctx &c);
 
 // adjoint (k_adjoint.hip)
 pic_status adjoint_seed(Ctx &c, double kb, double *lam, double *loss);

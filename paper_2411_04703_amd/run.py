@@ -24,6 +24,7 @@ def main(argv=None):
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-gauss", action="store_true", help="skip the FP64 Gauss-law residual (a full-grid pass)")
+    ap.add_argument("--init-fields", action="store_true", help="start from the beam's self-field (else zero fields)")
     a = ap.parse_args(argv)
 
     import torch
@@ -36,6 +37,8 @@ def main(argv=None):
     steps = a.steps if a.steps is not None else w["steps"]
     prec = abi.PIC_FP32_SPLIT if a.precision == "fp32" else abi.PIC_FP64_PLAIN
     opts = {} if prec == abi.PIC_FP32_SPLIT else {"max_steps": max(64, a.every)}
+    if a.init_fields:
+        opts["init_fields"] = 1
     t0 = time.perf_counter()
     sim = Sim(w, pin.beam_normals(w["beam"]["n_macro"], a.seed), precision=prec, **opts)
     sim.sync()

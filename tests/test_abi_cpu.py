@@ -100,6 +100,18 @@ def test_invalid_configurations_are_rejected(mutate, expect):
     assert e.value.status == expect
 
 
+def test_init_fields_option_is_validated():
+    w = pin.workload(0)
+    sim.query_layout(w, init_fields=1)
+    with pytest.raises(abi.PicError) as e:
+        sim.query_layout(w, init_fields=2)
+    assert e.value.status == abi.PIC_EINVAL
+    big = pin.scaled(w, nx=4096, ny=16, nz=16)
+    with pytest.raises(abi.PicError) as e:
+        sim.query_layout(big, init_fields=1)
+    assert e.value.status == abi.PIC_EINVAL
+
+
 @pytest.mark.parametrize("tile", [(4, 4, 4), (12, 8, 4), (8, 8, 32), (32, 32, 4)])
 def test_fp32_tiles_outside_the_built_set_are_rejected(tile):
     with pytest.raises(abi.PicError) as e:

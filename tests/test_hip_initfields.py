@@ -1,0 +1,103 @@
+"""GPU parity of the initial beam self-field (options.init_fields = 1): the
+FP64 relativistic Poisson solve of k_initfield.hip against the oracle's
+(FFT + tridiagonal in numpy), then the step from that field.
+
+Bars: FP64 fields 1e-11 of the field's norm at t' = 0 (two exact solvers in
+FP64 with different summation orders: O(n) line DFTs against FFTs); the
+following FP64 steps 1e-12 per step as the other FP64 parity tests; FP32
+fields 1e-6 (FP32 storage and the split positions' rounding of the charge);
+Gauss's law at t' = 0 to 1e-13 of the gross charge density (FP64)."""
+import math
+
+import numpy as np
+import pytest
+
+import picinputs as pin
+from oracle import pyoracle as po
+from test_hip_fp64 import FIELDS, _case, _compare, _pair
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_built")]
+
+CASES = ["undulator_beam", "beam_plasma_ions", "ragged"]
+
+
+def _field_err(gpu, ref):
+    out = {}
+    for f in FIELDS:
+        a, b = gpu.field(f).astype(np.float64), ref.field(f)
+        nb = np.linalg.norm(b)
+        out[f] = np.linalg.norm(a - b) / nb if nb > 0 else np.abs(a).max()
+    return out
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fp64_initial_field_matches_oracle(case):
+    ref, gpu = _pair(_case(case), init_fields=1)
+    po.init_beam_fields(ref)
+    err = _field_err(gpu, ref)
+    assert np.linalg.norm(ref.field("Ex")) > 0
+    for f, e in err.items():
+        assert e <= 1e-11, (f, err)
+
+
+@pytest.mark.parametrize("case", ["beam_plasma_ions", "undulator_beam"])
+def test_fp64_steps_from_initial_field_match_oracle(case):
+    ref, gpu = _pair(_case(case), init_fields=1)
+    po.init_beam_fields(ref)
+    for n in (1, 4, 10):
+        k = n - ref.info().step
+        ref.step(k)
+        gpu.step(k)
+        _compare(ref, gpu, 1e-11 + 1e-12 * n, f"step {n}")
+
+
+def test_fp64_initial_field_satisfies_gauss_law():
+    """div E - rho at t' = 0, against the gross density (plasma electrons and
+    ions cancel to round-off of gamma_R n0) or the net one, whichever is larger."""
+    from paper_2411_04703_amd import abi
+    from paper_2411_04703_amd.sim import derive
+    w = _case("beam_plasma_ions")
+    _, gpu = _pair(w, init_fields=1)
+    d = gpu.diag(abi.PIC_DIAG_GAUSS)
+    dv = derive(pin.scaled(w))
+    scale = max(d["rho_max"], dv["gamma_R"] * dv["n0_norm"])
+    assert d["rho_max"] > 0
+    assert d["gauss_max"] <= 1e-13 * scale, (d["gauss_max"], d["rho_max"], scale)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fp32_initial_field_matches_oracle(case):
+    from paper_2411_04703_amd.sim import Sim
+    w = _case(case)
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
+    ref = po.Sim(w, nrm)
+    po.init_beam_fields(ref)
+    w = pin.scaled(w)
+    w["frame"]["window_beta"] = ref.info().bw
+    s32 = Sim(w, nrm, precision=1, init_fields=1)
+    err = _field_err(s32, ref)
+    for f, e in err.items():
+        assert e <= 1e-6, (f, err)
+
+
+def test_fp32_tracks_fp64_from_initial_field():
+    from paper_2411_04703_amd.sim import Sim
+    w = _case("beam_plasma_ions")
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
+    w = pin.scaled(w)
+    w["frame"]["window_beta"] = po.Sim(w, nrm).info().bw
+    s32 = Sim(w, nrm, precision=1, init_fields=1)
+    s64 = Sim(w, nrm, precision=0, init_fields=1, max_steps=64)
+    s32.step(20)
+    s64.step(20)
+    # as for the zero-field start: FP32 rounds each step's field change relative to the gross
+    # (cancelling) plasma and ion currents
+    i = po.Sim(w, nrm).info()
+    gross = i.dt * i.gR * i.n0n * i.bR * math.sqrt(w["grid"]["nx"] * w["grid"]["ny"] * w["grid"]["nz"])
+    total = math.sqrt(sum(np.linalg.norm(s64.field(f)) ** 2 for f in FIELDS))
+    for f in FIELDS:
+        err = np.linalg.norm(s32.field(f) - s64.field(f))
+        assert err <= 1e-4 * max(total, gross), (f, err, total, gross)
+    d32, d64 = s32.diag(), s64.diag()
+    for k in ("mean", "sigma", "usigma", "emit"):
+        np.testing.assert_allclose(d32[k], d64[k], rtol=1e-4, err_msg=k)
