@@ -73,7 +73,7 @@ def test_fp32_init_matches_fp64(case):
 
 
 @pytest.mark.parametrize("case", ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "plasma_only", "beam_only",
-                                  "static_window", "no_boost", "ragged"])
+                                  "static_window", "no_boost", "ragged", "planar_undulator"])
 def test_fp32_steps_track_fp64(case):
     ref, s32, s64, w, _ = _sims(_w(case))
     for n in (1, 5, 20):

@@ -59,6 +59,10 @@ def _case(name):
         w["frame"]["gamma_boost"] = 1.0001
         w["beam"]["charge_C"] = 3e-9
         return w
+    if name == "planar_undulator":  # planar lab field (0, B0 sin phi, 0) instead of the helical one
+        w = pin.workload(0)
+        w["undulator"]["kind"] = 2
+        return w
     if name == "ragged":  # non-power-of-two grid of 3 x 5 x 4 tiles (8 x 8 x 16), beam count not a multiple of 64
         w = pin.scaled(pin.workload(1), nx=24, ny=40, nz=64, n_beam=4099, sigma=(2, 3, 8))
         w["beam"]["charge_C"] = 3e-9
@@ -67,7 +71,7 @@ def _case(name):
 
 
 CASES = ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "ramp_channel", "plasma_only", "beam_only",
-         "static_window", "no_boost", "ragged"]
+         "static_window", "no_boost", "ragged", "planar_undulator"]
 
 
 def _pair(w, seed=0, **opts):

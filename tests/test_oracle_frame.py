@@ -163,6 +163,34 @@ def test_external_field_invariants_and_period():
     assert abs(B0 - 1.3 * 2 * math.pi * dx / 0.02) < 1e-14
 
 
+def test_planar_external_field_structure():
+    """Planar lab field B = (0, B0 sin phi, 0) through Eq. M1-M4: B' = (0, gR B_y, 0),
+    E' = (-bR B'_y, 0, 0), peak |B'_y| = gR B0, spatial period lambda_u / gR, pattern
+    drifting at -beta_R (Eq. Vprime)."""
+    w = _small(n=16)
+    gR = 50.0
+    w["frame"]["gamma_boost"] = gR
+    w["undulator"].update(kind=2, K=1.3, period_lab_m=0.02, z_start_lab_m=-1.0, length_lab_m=10.0,
+                          entrance_ramp_periods=0.0)
+    s = po.Sim(w, pin.beam_normals(16, 0))
+    i = s.info()
+    dx = w["grid"]["dx_m"]
+    per_cells = 0.4e-3 / dx
+    peak = 0.0
+    for z in np.linspace(10, 10 + per_cells, 41):
+        for t in (0.0, 3.7):
+            E, B = _ext(s, z, t)
+            assert B[0] == 0.0 and B[2] == 0.0 and E[1] == 0.0 and E[2] == 0.0
+            assert abs(E[0] + i.bR * B[1]) < 1e-12 * i.B0 * gR
+            peak = max(peak, abs(B[1]))
+            E2, B2 = _ext(s, z + per_cells, t)
+            np.testing.assert_allclose(B2, B, atol=1e-9 * i.B0 * gR)
+            dt = 1.234
+            E3, B3 = _ext(s, z - i.bR * dt, t + dt)
+            np.testing.assert_allclose(B3, B, atol=1e-9 * i.B0 * gR)
+    assert abs(peak - gR * i.B0) < 2e-3 * gR * i.B0  # 41 samples per period: cos(pi/40) = 0.9969
+
+
 def test_lab_static_particle_is_force_free_under_vay():
     """A particle at rest in the lab has u' = -gR bR z; with E' + v' x B' = 0 the Vay pusher
     keeps it exactly (Vay 2008); Boris does not."""
