@@ -114,6 +114,45 @@ __device__ inline int reserve_slot(bool active, int key, int32_t *cnt) {
     return slot;
 }
 
+// The same reservation in two phases, so that its atomic's round trip can
+// overlap other work: reserve_issue groups the lanes by key and lets each
+// group's first lane add the group size (one atomic instruction for all
+// groups); reserve_slot_of, called later, hands every lane its slot.
+struct SlotTicket {
+    int lr;    // group leader lane | rank within the group << 8
+    int base;  // the group's first slot (in the leader lane)
+};
+
+__device__ inline SlotTicket reserve_issue(bool active, int key, int32_t *cnt) {
+    const int lane = __lane_id();
+    SlotTicket t{lane, 0};
+    bool pending = active, lead = false;
+    int size = 0;
+    unsigned long long todo = __ballot(pending);
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int lkey = __shfl(key, leader);
+        const bool grp = pending && key == lkey;
+        const unsigned long long gm = __ballot(grp);
+        if (grp) {
+            t.lr = leader | __popcll(gm & ((1ull << lane) - 1ull)) << 8;
+            pending = false;
+        }
+        if (lane == leader) {
+            lead = true;
+            size = __popcll(gm);
+        }
+        todo &= ~gm;
+    }
+    if (lead) t.base = atomicAdd(&cnt[key], size);
+    return t;
+}
+
+__device__ inline int reserve_slot_of(bool active, const SlotTicket &t) {
+    const int base = __shfl(t.base, t.lr & 63);
+    return active ? base + (t.lr >> 8) : -1;
+}
+
 struct OutStore {
     Part32 buf;
     const int64_t *off;
@@ -147,9 +186,18 @@ struct IOPair {
 
 // append (active lanes) to bin `bin` of the output store; overflow tail when the bin is full
 // (id_out: record mode, the particle id moves with it; null otherwise)
+__device__ inline void store_in_bin(const OutStore &O, bool active, int r, int bin, int cell, const float o[3],
+                                    const float u[3], float w, int32_t *flags, int32_t *id_out, int id);
+
 __device__ inline void append(const OutStore &O, bool active, int bin, int cell, const float o[3], const float u[3],
                               float w, int32_t *flags, int32_t *id_out, int id) {
-    int r = reserve_slot(active, active ? bin : 0, O.cnt);
+    const int r = reserve_slot(active, active ? bin : 0, O.cnt);
+    store_in_bin(O, active, r, bin, cell, o, u, w, flags, id_out, id);
+}
+
+// particle to rank r of bin `bin` (its reserved place), or to the overflow tail when the bin is full
+__device__ inline void store_in_bin(const OutStore &O, bool active, int r, int bin, int cell, const float o[3],
+                                    const float u[3], float w, int32_t *flags, int32_t *id_out, int id) {
     if (!active) return;
     int64_t b0 = gbl(O.off)[bin], cap = gbl(O.off)[bin + 1] - b0;
     int64_t s;
@@ -686,11 +734,16 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
 
         const LdsBoxT<G> box{Fs};
         for (int base = start; base < end; base += SST) {
-            bool act = base + tid < end;
+            // pushed: advanced (deposits its current); act: still in the band (appended)
+            bool act = base + tid < end, pushed = false;
             PState q;
+            float X0[3] = {0.0f, 0.0f, 0.0f}, X1[3] = {0.0f, 0.0f, 0.0f}, fq = 0.0f;
+            int li = 0, lj = 0, lk = 0;
             if (act) {
                 load_particle(IO.in, b0 + base + tid, P, q, REC ? iop.id[sp].in : nullptr);
-                const int li = q.i - t0x, lj = q.j - t0y, lk = q.l - t0z;
+                li = q.i - t0x;
+                lj = q.j - t0y;
+                lk = q.l - t0z;
                 const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
                                     q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
                                     q.o[2] >= 0.0f && q.o[2] < 1.0f;
@@ -699,42 +752,50 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                     atomicOr(flags, DFLAG_BIN_LOST);
                     act = false;
                 } else {
-                    float EB[6], X1[3];
+                    float EB[6];
                     gather6(box, q.o, li, lj, lk, EB);
                     if (!advance(P, EB, P.und_kind != 0, tabA[lk + 1], tabC[lk + 1], tabS[lk + 1], q, X1)) {
                         atomicOr(flags, DFLAG_NONFINITE);
                         act = false;
                     } else {
-                        Esk e;
-                        esk_setup(q.o, X1, e);
-                        float fq = q.w / (float)P.dt;
+                        fq = q.w / (float)P.dt;
                         if (!fixed_ok(fq, P.fscale)) {
                             atomicOr(flags, DFLAG_FIXED_OVERFLOW);
                             fq = 0.0f;
                         }
-                        // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2;
-                        // one base index per component, the node offsets are immediates
-                        const int bx = li + e.base[0] + 2, by = lj + e.base[1] + 2, bz = lk + e.base[2] + 2;
-                        const int jb[3] = {bx + G::XX * (by + G::XY * bz),
-                                           G::NJX + bx + G::YX * (by + G::YY * bz),
-                                           G::NJX + G::NJY + bx + G::ZX * (by + G::ZY * bz)};
-                        esk_visit<DEP>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
-                            int off;
-                            if (c == 0)  // (m, a, b) along (x, y, z)
-                                off = m + G::XX * (a + G::XY * b);
-                            else if (c == 1)  // (y, z, x)
-                                off = b + G::YX * (m + G::YY * a);
-                            else  // (z, x, y)
-                                off = a + G::ZX * (b + G::ZY * m);
-                            atomicAdd((unsigned long long *)&Js[jb[c] + off], (unsigned long long)iv);
-                        });
-                        for (int d = 0; d < 3; ++d) q.o[d] = X1[d];
+                        for (int d = 0; d < 3; ++d) {
+                            X0[d] = q.o[d];
+                            q.o[d] = X1[d];
+                        }
+                        pushed = true;
                         act = renormalise(P, S, q);
                     }
                 }
             }
-            append(IO.out, act, act ? bin_of(P, q.i, q.j, q.l) : 0, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o,
-                   q.u, q.w, flags, REC ? iop.id[sp].out : nullptr, q.id);
+            // destination slot: the reservation's atomic is in flight during the deposit
+            const int bin = act ? bin_of(P, q.i, q.j, q.l) : 0;
+            const SlotTicket tk = reserve_issue(act, bin, IO.out.cnt);
+            if (pushed) {
+                Esk e;
+                esk_setup(X0, X1, e);
+                // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2;
+                // one base index per component, the node offsets are immediates
+                const int bx = li + e.base[0] + 2, by = lj + e.base[1] + 2, bz = lk + e.base[2] + 2;
+                const int jb[3] = {bx + G::XX * (by + G::XY * bz), G::NJX + bx + G::YX * (by + G::YY * bz),
+                                   G::NJX + G::NJY + bx + G::ZX * (by + G::ZY * bz)};
+                esk_visit<DEP>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
+                    int off;
+                    if (c == 0)  // (m, a, b) along (x, y, z)
+                        off = m + G::XX * (a + G::XY * b);
+                    else if (c == 1)  // (y, z, x)
+                        off = b + G::YX * (m + G::YY * a);
+                    else  // (z, x, y)
+                        off = a + G::ZX * (b + G::ZY * m);
+                    atomicAdd((unsigned long long *)&Js[jb[c] + off], (unsigned long long)iv);
+                });
+            }
+            store_in_bin(IO.out, act, reserve_slot_of(act, tk), bin, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o, q.u,
+                         q.w, flags, REC ? iop.id[sp].out : nullptr, q.id);
         }
         __syncthreads();
         // flush nonzero LDS currents with global 64-bit integer atomics
