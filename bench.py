@@ -83,6 +83,75 @@ def cpu_baseline(seconds_budget: float = 20.0) -> dict:
                       f"particles, {steps} steps, single-threaded FP64 C"}
 
 
+def cpu_table():
+    """The oracle (one host core, FP64) beside the GPU paths on the small
+    workloads it can run: the 32x32x64 undulator workload in full (100 steps)
+    and the 16x16x64 adjoint case (100 steps forward, and forward + adjoint).
+    Prints one JSON line; the host's CPU model and core count are included."""
+    import math
+    import platform
+
+    import torch
+
+    import picinputs as pin
+    from oracle import build as ob
+    from oracle import pyoracle as po
+    from paper_2411_04703_amd import abi
+    from paper_2411_04703_amd.autograd import bunching_grad
+    from paper_2411_04703_amd.sim import Sim
+
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
+        ob.build()
+    model = platform.processor()
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    rows = []
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def gpu_forward(w, nrm, prec, nsteps):
+        s = Sim(w, nrm, precision=prec, **({} if prec else {"max_steps": 64}))
+        s.step(2)
+        s.sync()
+        d = s.diag()
+        dt = timed(lambda: (s.step(nsteps), s.sync()))
+        return (d["n_beam"] + d["n_plasma"]) * nsteps / dt
+
+    for name, w, nsteps in (("32x32x64 undulator beam, 16384 particles", pin.workload(0), 100),
+                            ("16x16x64 adjoint case (beam, undulator, plasma, ions)", pin.adjoint_subcase(), 100)):
+        nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
+        o = po.Sim(w, nrm)
+        i = o.info()
+        npart = i.n_beam + i.n_plasma
+        t0 = time.perf_counter()
+        o.step(nsteps)
+        orc = npart * nsteps / (time.perf_counter() - t0)
+        ww = pin.scaled(w)
+        ww["frame"]["window_beta"] = i.bw
+        row = {"workload": name, "steps": nsteps, "oracle_particle_steps_per_s": orc,
+               "oracle_cell_updates_per_s": orc / npart * o.nc,
+               "gpu_fp64_particle_steps_per_s": gpu_forward(ww, nrm, abi.PIC_FP64_PLAIN, nsteps),
+               "gpu_fp32_particle_steps_per_s": gpu_forward(ww, nrm, abi.PIC_FP32_SPLIT, nsteps)}
+        if "checkpoint_every" in w:
+            kb = 2 * math.pi / 20.0
+            t0 = time.perf_counter()
+            po.grad_bunching(w, nrm, nsteps, kb)
+            row["oracle_forward_adjoint_s"] = time.perf_counter() - t0
+            for key, prec in (("gpu_fp64_forward_adjoint_s", abi.PIC_FP64_PLAIN),
+                              ("gpu_fp32_mode_forward_adjoint_s", abi.PIC_FP32_SPLIT)):
+                row[key] = timed(lambda: bunching_grad(ww, nrm, nsteps, every=10, precision=prec))
+        rows.append(row)
+    print(json.dumps({"host_cpu": model, "host_cores": os.cpu_count(), "oracle_threads": 1, "rows": rows}),
+          flush=True)
+
+
 def copy_calibration(mib: int):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings calibrate
     the HBM-traffic counters of the particle kernel."""
@@ -114,9 +183,14 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="FP32 current-deposit variant (0, 1 or 2)")
     ap.add_argument("--tile", default="0,0,0", help="FP32 cell tile nx,ny,nz (0,0,0: the library's choice)")
     ap.add_argument("--wg-per-cu", type=int, default=0, help="FP32 particle-kernel workgroups per CU (0 = max)")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the oracle beside the GPU paths on the small workloads and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.cpu_table:
+        cpu_table()
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
