@@ -29,7 +29,7 @@ namespace pic {
 
 constexpr int ST = 512;    // threads per workgroup of the auxiliary kernels
 constexpr int SST = 768;   // threads per workgroup of the step kernel (3 waves per SIMD)
-constexpr int CH = 6 * SST;  // particles per work item
+constexpr int CH = 12 * SST;  // particles per work item (bins larger than this are split; measured best of 3-24 x SST)
 constexpr int WT = 512;    // threads of the work-list kernels
 constexpr int QPAD = 64;   // int32 stride of the slab queue counters: one 256-byte block each, apart from
                            // everything else (a counter sharing a cache line with the read-only queue
