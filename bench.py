@@ -152,6 +152,27 @@ def cpu_table():
           flush=True)
 
 
+def atomic_calibration(mega: int):
+    """64-bit integer atomic adds to distinct device addresses in random order
+    (torch index_add_): a reference rate, and a reference reading of the L2
+    atomic counters, for the particle kernel's current flush."""
+    import torch
+    n = mega * (1 << 20)
+    dst = torch.zeros(n, dtype=torch.int64, device="cuda")
+    idx = torch.randperm(n, device="cuda")
+    src = torch.ones(n, dtype=torch.int64, device="cuda")
+    for _ in range(2):
+        dst.index_add_(0, idx, src)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.index_add_(0, idx, src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"atomics": n, "ms": dt * 1e3, "atomics_per_s": n / dt}), flush=True)
+
+
 def copy_calibration(mib: int):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings calibrate
     the HBM-traffic counters of the particle kernel."""
@@ -185,6 +206,8 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0, help="FP32 particle-kernel workgroups per CU (0 = max)")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the oracle beside the GPU paths on the small workloads and exit")
+    ap.add_argument("--atomic-calibration", type=int, default=0, metavar="M",
+                    help="only time M x 2^20 int64 atomic adds to distinct addresses and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only time a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -193,6 +216,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.atomic_calibration:
+        atomic_calibration(args.atomic_calibration)
         return
     tile = tuple(int(v) for v in args.tile.split(","))
     if args.gpus != 1:
