@@ -168,3 +168,21 @@ def test_workload1_full_run_fp32_within_stated_tolerance():
     report["b1_abs"] = (eb, max(1e-6, 3.0 * sb))
     print("full-run tolerance report", report)
     assert eb <= max(1e-6, 3.0 * sb), report
+
+
+def test_workload1_stays_stable_over_two_and_a_half_runs():
+    """2500 steps of the FP32 path (2.5x the workload's length): the wake's field
+    energy peaks near step 1000 and then decays; no growing mode (the moving
+    window's front face keeps its tangential E, see the Mur treatment)."""
+    from paper_2411_04703_amd import abi
+    s = _gpu()
+    fe = []
+    for _ in range(25):
+        s.step(100)
+        d = s.diag(abi.PIC_DIAG_ENERGY | abi.PIC_DIAG_MOMENTS)
+        assert math.isfinite(d["field_energy"]) and d["error_flags"] == 0
+        fe.append(d["field_energy"])
+    peak = max(fe[:12])
+    assert max(fe[12:]) <= 1.1 * peak, fe
+    assert fe[-1] < peak, fe
+    assert s.diag()["n_beam"] == W["beam"]["n_macro"]
