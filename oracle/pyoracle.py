@@ -347,3 +347,43 @@ def init_beam_fields(sim: "Sim"):
     for name, v in zip(FIELD_NAMES, E + B):
         sim.field(name)[:] = v
     return beta, gamma
+
+
+# ---------------------------------------------------------------------------
+# Lab-frame probe (section 2: relating the boosted frame's data to the lab).
+# A particle at boosted position z' and time t' is at lab time
+# t = gR (t' + bR (z' - z0)) and lab position z_lab = gR (z' - z0 + bR t'),
+# z0 being the boosted-grid offset of the beam centre (lab origin at the beam
+# centre at lab time 0).  Over a step a particle moves on a straight line, so
+# the instant its lab time passes T is found on that line and its lab
+# position taken there.  Every beam particle is sampled once.
+def lab_probe(sim: "Sim", nsteps: int, t_lab: float, k_lab: float) -> dict:
+    """Advance nsteps steps; return the sums over sampled beam particles of w,
+    w cos(k z_lab), w sin(k z_lab), w z_lab, w z_lab^2, and per beam slot the
+    sampled lab x, z (NaN where not sampled)."""
+    i = sim.info()
+    gR, bR, dt, z0c = i.gR, i.bR, i.dt, i.zoff
+    p = sim.particles(0)
+    n = len(p["z"])
+    xs = np.full(n, np.nan)
+    zs = np.full(n, np.nan)
+    for _ in range(nsteps):
+        t0 = sim.info().step * dt
+        x0, z0, a0 = np.real(p["x"]), np.real(p["z"]), p["alive"] == 1
+        sim.step(1)
+        p = sim.particles(0)
+        x1, z1, a1 = np.real(p["x"]), np.real(p["z"]), p["alive"] == 1
+        t1 = t0 + dt
+        tl0 = gR * (t0 + bR * (z0 - z0c))
+        tl1 = gR * (t1 + bR * (z1 - z0c))
+        m = a0 & a1 & np.isnan(zs) & (tl0 <= t_lab) & (t_lab < tl1)
+        f = (t_lab - tl0[m]) / (tl1[m] - tl0[m])
+        zc = z0[m] + f * (z1[m] - z0[m])
+        tc = t0 + f * dt
+        zs[m] = gR * (zc - z0c + bR * tc)
+        xs[m] = x0[m] + f * (x1[m] - x0[m])
+    w = np.real(sim.particles(0)["w"])
+    s = ~np.isnan(zs)
+    ws, zz = w[s], zs[s]
+    return {"w": ws.sum(), "c": (ws * np.cos(k_lab * zz)).sum(), "s": (ws * np.sin(k_lab * zz)).sum(),
+            "z": (ws * zz).sum(), "zz": (ws * zz * zz).sum(), "x_lab": xs, "z_lab": zs}
