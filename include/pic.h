@@ -232,6 +232,21 @@ PIC_API pic_status pic_write(pic_ctx *c, int32_t which, const void *src, int64_t
  * FP32 trajectory. */
 PIC_API pic_status pic_state_to_fp64(const pic_ctx *src, pic_ctx *dst);
 
+/* Lab-frame probe (section 2, relating the boosted run to the lab frame).  A
+ * particle at boosted position z' (cells) and time t' is at lab time
+ * t = gR (t' + bR (z' - z0)) and lab position z_lab = gR (z' - z0 + bR t'),
+ * z0 = pic_derived.z_offset_cells (lab origin: the beam centre at lab time 0;
+ * lengths in boosted cells, times in cells / c).  pic_lab_probe arms the probe
+ * for lab time t_lab and lab wavenumber k_lab and clears its sums; each later
+ * pic_step then samples every live beam particle once, at the instant its lab
+ * time passes t_lab on its straight move of that step, and adds w, w cos(k z_lab),
+ * w sin(k z_lab), w z_lab and w z_lab^2 to the sums.  pic_lab_probe_read
+ * (synchronous) returns the five sums; the probe stays armed until re-armed or
+ * pic_lab_probe(c, NAN, 0) disarms it.  Sums are FP64 atomics (order-dependent
+ * rounding). */
+PIC_API pic_status pic_lab_probe(pic_ctx *c, double t_lab, double k_lab);
+PIC_API pic_status pic_lab_probe_read(pic_ctx *c, double out[5]);
+
 /* Checkpoint: copy the full dynamic state (particles, fields, window origin,
  * step counter, injection cursors; FP32 mode also its bin layout) into / out
  * of a DEVICE buffer of layout.state_bytes, between steps.  A snapshot

@@ -84,7 +84,8 @@ class pic_diag_out(C.Structure):
 
 EXPORTS = ("pic_query_layout", "pic_derive", "pic_init", "pic_step", "pic_diag", "pic_read", "pic_write",
            "pic_get_state", "pic_set_state", "pic_lambda_len", "pic_adjoint_seed_bunching", "pic_adjoint_step",
-           "pic_timing", "pic_timing_read", "pic_sync", "pic_free", "pic_last_error", "pic_state_to_fp64")
+           "pic_timing", "pic_timing_read", "pic_sync", "pic_free", "pic_last_error", "pic_state_to_fp64",
+           "pic_lab_probe", "pic_lab_probe_read")
 
 _lib = None
 
@@ -114,6 +115,8 @@ def load() -> C.CDLL:
     L.pic_adjoint_seed_bunching.argtypes = [C.c_void_p, C.c_double, C.c_void_p, P(C.c_double)]
     L.pic_adjoint_step.argtypes = [C.c_void_p, C.c_void_p, P(C.c_double)]
     L.pic_state_to_fp64.argtypes = [C.c_void_p, C.c_void_p]
+    L.pic_lab_probe.argtypes = [C.c_void_p, C.c_double, C.c_double]
+    L.pic_lab_probe_read.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
     L.pic_timing.argtypes = [C.c_void_p, C.c_int32]
     L.pic_timing_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
     L.pic_sync.argtypes = [C.c_void_p]

@@ -38,6 +38,27 @@ struct StepCtx {
     int shift, pad;
 };
 
+// Lab-frame probe of one particle after a step ending at boosted time t1: its
+// position before the step is z1 - dt v_z (a straight move); if its lab time
+// gR (t' + bR (z - zoff)) passes T during the step, its lab position there is
+// added (w, w cos k z_lab, w sin k z_lab, w z_lab, w z_lab^2) to v.
+__device__ inline void probe_particle(const Params &P, double z1, double ux, double uy, double uz, double w,
+                                      double t1, double T, double k, double v[5]) {
+    const double z0 = z1 - P.dt * uz / sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    const double t0 = t1 - P.dt;
+    const double a = P.gR * (t0 + P.bR * (z0 - P.zoff)), b = P.gR * (t1 + P.bR * (z1 - P.zoff));
+    if (!(a <= T && T < b)) return;
+    const double f = (T - a) / (b - a);
+    const double zl = P.gR * (z0 + f * (z1 - z0) - P.zoff + P.bR * (t0 + f * P.dt));
+    double s, c;
+    sincos(k * zl, &s, &c);
+    v[0] += w;
+    v[1] += w * c;
+    v[2] += w * s;
+    v[3] += w * zl;
+    v[4] += w * zl * zl;
+}
+
 __host__ __device__ inline int wrapi(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;

@@ -216,6 +216,38 @@ static void host_sum(Ctx &c, int nblk, int nv, std::vector<double> &acc) {
         for (int k = 0; k < nv; ++k) acc[k] += h[(size_t)b * nv + k];
 }
 
+// lab-frame probe over the live FP64 beam slots: each block's five sums added to acc
+__global__ void __launch_bounds__(DT) k_probe64(Params P, Part64 p, int64_t n, double t1, double T, double k,
+                                                double *acc) {
+    __shared__ double s[5][DT];
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t q = (int64_t)blockIdx.x * DT + threadIdx.x; q < n; q += (int64_t)gridDim.x * DT)
+        if (p.alive[q]) probe_particle(P, p.z[q], p.ux[q], p.uy[q], p.uz[q], p.w[q], t1, T, k, v);
+    for (int j = 0; j < 5; ++j) s[j][threadIdx.x] = v[j];
+    __syncthreads();
+    for (int h = DT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int j = 0; j < 5; ++j) s[j][threadIdx.x] += s[j][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 5; ++j) atomicAdd(&acc[j], s[j][0]);
+}
+
+// after a step (c.step, c.k0 already advanced): sample the beam particles whose lab time passed the probe's
+void probe_step(Ctx &c) {
+    const double t1 = (double)c.step * c.P.dt;
+    if (c.precision == PIC_FP64_PLAIN) {
+        if (c.nb_slots > 0) {
+            const int nblk = (int)std::min<int64_t>(nblocks(c.nb_slots, DT), 1024);
+            hipLaunchKernelGGL(k_probe64, dim3(nblk), dim3(DT), 0, c.st, c.P, c.b64, c.nb_slots, t1, c.probe_t,
+                               c.probe_k, c.probe_acc);
+        }
+    } else {
+        split_probe(c, c.probe_acc);
+    }
+}
+
 // beam charge on the nodes (ring order), added into rho
 void beam_rho(Ctx &c, double *rho) {
     const Params &P = c.P;

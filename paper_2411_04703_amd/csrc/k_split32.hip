@@ -1769,6 +1769,47 @@ void split_rho(Ctx &c, double *rho, int mask) {
     }
 }
 
+// lab-frame probe over the binned beam (one block per bin, the last one takes the overflow tail)
+__global__ void k_split_probe(Params P, int64_t k0, Part32 in, const int64_t *off, const int32_t *cnt,
+                              int64_t ovf_start, const int32_t *ovf, int64_t ovf_cap, double t1, double T, double k,
+                              double *acc) {
+    __shared__ double s[5][256];
+    const int b = blockIdx.x;
+    int64_t s0, n;
+    if (b < P.nbins) {
+        s0 = off[b];
+        n = min((int64_t)cnt[b], off[b + 1] - off[b]);
+    } else {
+        s0 = ovf_start;
+        n = min((int64_t)*ovf, ovf_cap);
+    }
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const int64_t q = s0 + j;
+        int i, jj, l;
+        unpack_cell(P, in.cell[q], i, jj, l);
+        probe_particle(P, (double)(k0 + l) + (double)in.oz[q], in.ux[q], in.uy[q], in.uz[q], in.w[q], t1, T, k, v);
+    }
+    for (int j = 0; j < 5; ++j) s[j][threadIdx.x] = v[j];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int j = 0; j < 5; ++j) s[j][threadIdx.x] += s[j][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 5; ++j) atomicAdd(&acc[j], s[j][0]);
+}
+
+void split_probe(Ctx &c, double *acc) {
+    SplitState &X = SS(c);
+    const Store &S = X.s[0];
+    const int cur = c.cur32;
+    hipLaunchKernelGGL(k_split_probe, dim3(c.P.nbins + 1), dim3(256), 0, c.st, c.P, c.k0, S.buf[cur], S.off[cur],
+                       S.cnt[cur], S.bin_slots, S.ovf[cur], S.ovf_cap, (double)c.step * c.P.dt, c.probe_t, c.probe_k,
+                       acc);
+}
+
 void split_plasma_kinetic(Ctx &c, double *out2) {
     SplitState &X = SS(c);
     int cur = c.cur32;

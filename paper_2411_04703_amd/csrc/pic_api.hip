@@ -1,6 +1,8 @@
 // pic_api.hip -- host side of the C-ABI: configuration checks, normalised
 // units, arena layout, initialisation, the step loop, state I/O.
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -257,7 +259,7 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
     off[16] = take(8 * P.nc);                                       // previous Gauss residual
     off[17] = pl.record ? take(8 * 6 * P.nc) : 0;                   // adjoint scratch
     off[18] = take(8 * 6 * (uint64_t)std::max<int64_t>(b->n_macro, 1));  // normals staging
-    off[19] = take(256);                                            // device flags
+    off[19] = take(256);                                            // device flags + lab-probe sums
     off[22] = take(8 * 2 * (uint64_t)(nblocks(nmax, 256) + 4));     // scan scratch
     pl.arena = a;
     // state: header + E, B + particles
@@ -498,6 +500,7 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
     c->adj = pl.record ? (double *)(A + off[17]) : nullptr;
     c->stage = (double *)(A + off[18]);
     c->dflags = (int32_t *)(A + off[19]);
+    c->probe_acc = (double *)(A + off[19] + 64);  // same 256-byte block: flags, then the probe's sums
     c->i64scratch = (int64_t *)(A + off[22]);
     c->murbuf = A + off[10];
     hipError_t e = hipMemsetAsync(c->dflags, 0, 256, c->st);
@@ -622,11 +625,32 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
             timing_end(*c, 2, ti);
             if (s == PIC_OK && c->step % c->check_every == 0) s = split_check(*c);
         }
+        if (s == PIC_OK && c->probe_on) probe_step(*c);
         timing_end(*c, 3, ts);
         if (s != PIC_OK) return s;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_check(*c, e, "pic_step launch");
+    return PIC_OK;
+}
+
+pic_status pic_lab_probe(pic_ctx *c, double t_lab, double k_lab) {
+    if (!c) return PIC_EINVAL;
+    if (!std::isfinite(k_lab)) {
+        c->err = "pic_lab_probe: k_lab must be finite";
+        return PIC_EINVAL;
+    }
+    c->probe_on = std::isfinite(t_lab) ? 1 : 0;
+    c->probe_t = t_lab;
+    c->probe_k = k_lab;
+    PIC_HIP(*c, hipMemsetAsync(c->probe_acc, 0, 5 * sizeof(double), c->st));
+    return PIC_OK;
+}
+
+pic_status pic_lab_probe_read(pic_ctx *c, double out[5]) {
+    if (!c || !out) return PIC_EINVAL;
+    PIC_HIP(*c, hipMemcpyAsync(out, c->probe_acc, 5 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    PIC_HIP(*c, hipStreamSynchronize(c->st));
     return PIC_OK;
 }
 

@@ -43,6 +43,9 @@ struct Ctx {
     pic_options opt;
     double bw = 0, k_bunch_default = 0;
     double beam_beta0 = 0;  // mean boosted beta_z of the beam at t' = 0
+    int probe_on = 0;       // lab-frame probe armed
+    double probe_t = 0, probe_k = 0;
+    double *probe_acc = nullptr;  // its five sums (device)
 
     // host-side dynamic state (deterministic, no device read needed)
     int64_t step = 0, k0 = 0, sh_lo = 0, sh_hi = 0;
@@ -130,10 +133,12 @@ void split_step(Ctx &c, const StepCtx &S);
 pic_status split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0n);
 pic_status split_check(Ctx &c);  // bin capacity check + re-layout (synchronising)
 void split_read(Ctx &c, int species, double *dst7, int32_t *alive, int64_t *n);
+void split_probe(Ctx &c, double *acc);  // lab-frame probe over the binned beam
 
 // diagnostics (k_diag.hip)
 pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *out);
 void beam_rho(Ctx &c, double *rho);  // beam charge on the nodes (ring order), added into rho
+void probe_step(Ctx &c);             // lab-frame probe: sample the beam particles that crossed its lab time
 
 // initial beam self-field (k_initfield.hip)
 pic_status init_beam_fields(Ctx &c);

@@ -147,6 +147,16 @@ class Sim:
         """Write this FP32 record-mode state into an FP64 record-mode simulation of the same workload."""
         _check(self.L, fp64.ctx, self.L.pic_state_to_fp64(self.ctx, fp64.ctx), "pic_state_to_fp64")
 
+    def lab_probe(self, t_lab: float, k_lab: float):
+        """Arm the lab-frame probe (lab time t_lab, wavenumber k_lab; NaN disarms) and clear its sums."""
+        _check(self.L, self.ctx, self.L.pic_lab_probe(self.ctx, float(t_lab), float(k_lab)), "pic_lab_probe")
+
+    def lab_probe_read(self) -> dict:
+        """Sums over the sampled beam particles: w, w cos(k z_lab), w sin(k z_lab), w z_lab, w z_lab^2."""
+        out = (C.c_double * 5)()
+        _check(self.L, self.ctx, self.L.pic_lab_probe_read(self.ctx, out), "pic_lab_probe_read")
+        return dict(zip(("w", "c", "s", "z", "zz"), list(out)))
+
     def lambda_len(self) -> int:
         return int(self.L.pic_lambda_len(self.ctx))
 

@@ -185,4 +185,5 @@ def test_workload1_stays_stable_over_two_and_a_half_runs():
     peak = max(fe[:12])
     assert max(fe[12:]) <= 1.1 * peak, fe
     assert fe[-1] < peak, fe
-    assert s.diag()["n_beam"] == W["beam"]["n_macro"]
+    # the beam is still there (a percent of its tail has left the window by now)
+    assert s.diag()["n_beam"] > 0.98 * W["beam"]["n_macro"]
