@@ -73,8 +73,8 @@ typedef struct {
     double gamma_boost, window_beta;
 } pic_frame;
 
-/* Electron beam defined in the lab at lab time 0 (section 3: "after definition
- * in the LRF the code calculates the equivalence to the RRF").  Gaussian with rms
+/* Electron beam defined in the lab at lab time 0 and converted by the library
+ * into the boosted frame (as section 3 describes).  Gaussian with rms
  * sizes sigma_cells[0..1] (transverse, frame invariant, cells) and sigma_cells[2]
  * (longitudinal, boosted-frame cells; the lab rms length follows from Eq. Belon),
  * lab Lorentz factor gamma_lab with relative rms spread, normalised rms emittances

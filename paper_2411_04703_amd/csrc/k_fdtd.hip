@@ -6,10 +6,11 @@
 //   E <- E + dt (curl B - J)
 // Yee staggering: Ex(i+1/2,j,k) Ey(i,j+1/2,k) Ez(i,j,k+1/2), Bx(i,j+1/2,k+1/2)
 // By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k).  x, y periodic.  z: nz logical planes
-// stored as a ring (logical plane l lives in ring plane (l + k0) mod nz), the
-// field is absorbed at the z faces by the first-order Mur condition on the
-// tangential E (the paper: "the fields are absorbed upon interaction with the
-// boundaries"), and the half planes beyond the front face stay zero.
+// stored as a ring (logical plane l lives in ring plane (l + k0) mod nz).  The
+// z boundaries absorb (section 1): first-order Mur on the tangential E at the
+// back face, and at the front face while the window is at rest; a moving
+// window's front face keeps its tangential E, and the half planes beyond it
+// stay zero.
 // One thread per cell, x fastest: every array access is coalesced along x.
 #include "pic_internal.h"
 
