@@ -238,9 +238,14 @@ __device__ inline void unpack_cell(const Params &P, int cell, int &i, int &j, in
 }
 
 // periodic wrap of an index at most one period outside [0, n)
-__device__ inline int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// periodic wrap; a grid narrower than a tile's box (a 2D grid, ny = 1) wraps more than once
+__device__ inline int wrap1(int i, int n) {
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
+    return i;
+}
 
-// linear index of cell (i, j, ring plane p), i and j at most one period outside the grid
+// linear index of cell (i, j, ring plane p), i and j outside the grid wrapped periodically
 __device__ inline int64_t near_cell(const Params &P, int i, int j, int p) {
     return (int64_t)wrap1(i, P.nx) + (int64_t)P.nx * ((int64_t)wrap1(j, P.ny) + (int64_t)P.ny * p);
 }
@@ -835,7 +840,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
 }
 
 // the tiles the step kernel is instantiated for
-#define PIC_SPLIT_TILES(X) X(8, 8, 4) X(8, 8, 8) X(8, 8, 16) X(16, 8, 4) X(16, 16, 4) X(16, 8, 8)
+#define PIC_SPLIT_TILES(X) X(8, 8, 4) X(8, 8, 8) X(8, 8, 16) X(16, 8, 4) X(16, 16, 4) X(16, 8, 8) X(16, 1, 16)
 
 using StepKernel = void (*)(Params, StepCtx, const int4 *, const int32_t *, int32_t *, int, IOPair,
                             FieldsT<float>, long long *, long long *, long long *, int32_t *, const double *,

@@ -133,19 +133,23 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
         int t[3] = {o->tile[0], o->tile[1], o->tile[2]};
         if (!t[0] && !t[1] && !t[2]) {
             // largest tile (least halo per cell) that divides the grid, by measured speed
-            static const int pref[6][3] = {{16, 16, 4}, {16, 8, 8}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4}};
-            for (int k = 0; k < 6; ++k)
+            // (16 x 1 x 16: two-dimensional x-z grids, ny = 1)
+            static const int pref[7][3] = {{16, 16, 4}, {16, 8, 8}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4},
+                                           {16, 1, 16}};
+            for (int k = 0; k < 7; ++k)
                 if (g->nx % pref[k][0] == 0 && g->ny % pref[k][1] == 0 && g->nz % pref[k][2] == 0) {
                     t[0] = pref[k][0];
                     t[1] = pref[k][1];
                     t[2] = pref[k][2];
                     break;
                 }
-            if (!t[0]) return fail(err, PIC_EINVAL, "FP32 mode: grid edges must be multiples of 8, 8, 4");
+            if (!t[0])
+                return fail(err, PIC_EINVAL, "FP32 mode: grid edges must be multiples of 8, 8, 4 (or 16, 1, 16)");
         }
         if (g->nx % t[0] || g->ny % t[1] || g->nz % t[2])
             return fail(err, PIC_EINVAL, "options: tile must divide the grid");
-        if (t[0] < 4 || t[1] < 4 || t[2] < 4) return fail(err, PIC_EINVAL, "options: tile edges >= 4");
+        if (t[0] < 4 || t[2] < 4 || (t[1] < 4 && !(t[1] == 1 && g->ny == 1)))
+            return fail(err, PIC_EINVAL, "options: tile edges >= 4 (y edge 1 on a grid with ny = 1)");
         auto lg = [](int v) { int k = 0; while ((1 << k) < v) ++k; return k; };
         for (int d3 = 0; d3 < 3; ++d3)
             if (t[d3] != (1 << lg(t[d3]))) return fail(err, PIC_EINVAL, "options: tile edges must be powers of two");
@@ -154,7 +158,7 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
         if (P.cbx + P.cby + lg(g->nz) > 31) return fail(err, PIC_EINVAL, "FP32 mode: grid needs more than 31 cell bits");
         if (!split_tile_supported(t[0], t[1], t[2]))
             return fail(err, PIC_EINVAL,
-                        "options: FP32 tile must be one of 8x8x4, 8x8x8, 8x8x16, 16x8x4, 16x16x4, 16x8x8");
+                        "options: FP32 tile must be one of 8x8x4, 8x8x8, 8x8x16, 16x8x4, 16x16x4, 16x8x8, 16x1x16");
         P.lgx = lg(t[0]);
         P.lgy = lg(t[1]);
         P.lgz = lg(t[2]);

@@ -79,7 +79,7 @@ def _with_plasma(w, n0_cm3, ppc, uniform=True, z_start_m=0.0, length_m=0.0, ramp
 
 
 def workload(idx: int) -> dict:
-    """The five hot-path workloads, 0..4."""
+    """The five hot-path workloads, 0..4, and a two-dimensional one, 5."""
     if idx == 0:
         # FP64 parity case: beam in a helical undulator, no plasma.
         w = _base(32, 32, 64, 10.0, 16_384, (4, 4, 8), 100)
@@ -107,6 +107,13 @@ def workload(idx: int) -> dict:
         w = _base(512, 512, 2048, 40.0, 33_554_432, (4, 4, 32), 20000)
         w = _with_undulator(w, K=1.0, length_m=2.0)
         return _with_plasma(w, 1e16, (1, 1, 2))
+    if idx == 5:
+        # Two-dimensional x-z counterpart of the paper's combined case (its runs are 2D):
+        # planar undulator plus uniform plasma at gamma_R = 10, 2048 x 1 x 4096 cells, 4 ppc.
+        w = _base(2048, 1, 4096, 10.0, 4_194_304, (4, 1, 32), 2000)
+        w = _with_undulator(w, K=1.0, length_m=2.0)
+        w["undulator"]["kind"] = 2
+        return _with_plasma(w, 3e15, (2, 1, 2))
     raise ValueError(idx)
 
 

@@ -119,6 +119,13 @@ def test_fp32_tiles_outside_the_built_set_are_rejected(tile):
     assert e.value.status == abi.PIC_EINVAL
 
 
+def test_two_dimensional_grids_take_the_x_z_tile():
+    w = pin.scaled(pin.workload(1), nx=32, ny=1, nz=64)
+    assert sim.derive(w, precision=abi.PIC_FP32_SPLIT)["tile"] == [16, 1, 16]
+    with pytest.raises(abi.PicError):
+        sim.derive(pin.scaled(pin.workload(1), nx=32, ny=16, nz=64), precision=abi.PIC_FP32_SPLIT, tile=(16, 1, 16))
+
+
 @pytest.mark.parametrize("tile", [(8, 8, 4), (8, 8, 8), (8, 8, 16), (16, 8, 4), (16, 16, 4), (16, 8, 8)])
 def test_fp32_built_tiles_are_accepted(tile):
     assert sim.query_layout(pin.workload(1), precision=abi.PIC_FP32_SPLIT, tile=tile).arena_bytes > 0

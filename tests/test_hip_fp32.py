@@ -73,7 +73,8 @@ def test_fp32_init_matches_fp64(case):
 
 
 @pytest.mark.parametrize("case", ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "plasma_only", "beam_only",
-                                  "static_window", "no_boost", "ragged", "planar_undulator"])
+                                  "static_window", "no_boost", "ragged", "planar_undulator", "plane_2d",
+                                  "planar_2d"])
 def test_fp32_steps_track_fp64(case):
     ref, s32, s64, w, _ = _sims(_w(case))
     for n in (1, 5, 20):
@@ -189,6 +190,22 @@ def test_fp32_tiles_and_deposit_variants_agree_bitwise():
             assert np.array_equal(fields[f], runs[0][0][f]), (tag, f)
         for sp in (0, 1):
             assert np.array_equal(parts[sp], runs[0][1][sp]), (tag, sp)
+
+
+def test_fp32_two_dimensional_variants_agree_bitwise():
+    """The x-z tile (16 x 1 x 16) with every deposit variant: identical integer currents."""
+    from paper_2411_04703_amd.sim import Sim
+    from test_hip_fp64 import _case
+    w = _case("plane_2d")
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 2)
+    runs = []
+    for variant in (0, 1, 2):
+        s = Sim(w, nrm, precision=1, variant=variant)
+        s.step(15)
+        runs.append({f: s.field(f) for f in FIELDS})
+    for r in runs[1:]:
+        for f in FIELDS:
+            assert np.array_equal(r[f], runs[0][f]), f
 
 
 def test_fp32_checkpoint_resume_is_bitwise():

@@ -63,6 +63,15 @@ def _case(name):
         w = pin.workload(0)
         w["undulator"]["kind"] = 2
         return w
+    if name == "plane_2d":  # two-dimensional x-z grid (ny = 1), as the paper's runs: beam, plasma, ions
+        w = pin.scaled(pin.workload(1), nx=32, ny=1, nz=64, n_beam=2048, sigma=(2, 1, 8))
+        w["beam"]["charge_C"] = 3e-10
+        return w
+    if name == "planar_2d":  # planar undulator on the x-z grid
+        w = pin.scaled(pin.workload(0), ny=1, n_beam=4096)
+        w["undulator"]["kind"] = 2
+        w["beam"]["charge_C"] = 3e-10
+        return w
     if name == "ragged":  # non-power-of-two grid of 3 x 5 x 4 tiles (8 x 8 x 16), beam count not a multiple of 64
         w = pin.scaled(pin.workload(1), nx=24, ny=40, nz=64, n_beam=4099, sigma=(2, 3, 8))
         w["beam"]["charge_C"] = 3e-9
@@ -71,7 +80,7 @@ def _case(name):
 
 
 CASES = ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "ramp_channel", "plasma_only", "beam_only",
-         "static_window", "no_boost", "ragged", "planar_undulator"]
+         "static_window", "no_boost", "ragged", "planar_undulator", "plane_2d", "planar_2d"]
 
 
 def _pair(w, seed=0, **opts):
