@@ -238,16 +238,12 @@ __device__ inline void unpack_cell(const Params &P, int cell, int &i, int &j, in
 }
 
 // periodic wrap of an index at most one period outside [0, n)
-// periodic wrap; a grid narrower than a tile's box (a 2D grid, ny = 1) wraps more than once
-__device__ inline int wrap1(int i, int n) {
-    while (i < 0) i += n;
-    while (i >= n) i -= n;
-    return i;
-}
+__device__ inline int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// linear index of cell (i, j, ring plane p), i and j outside the grid wrapped periodically
-__device__ inline int64_t near_cell(const Params &P, int i, int j, int p) {
-    return (int64_t)wrap1(i, P.nx) + (int64_t)P.nx * ((int64_t)wrap1(j, P.ny) + (int64_t)P.ny * p);
+// linear index of cell (i, j, ring plane p), i and j at most one period outside the grid;
+// NY1: a two-dimensional x-z grid (ny = 1, tile edge 1 in y), where every j is row 0
+template <bool NY1 = false> __device__ inline int64_t near_cell(const Params &P, int i, int j, int p) {
+    return (int64_t)wrap1(i, P.nx) + (int64_t)P.nx * ((NY1 ? (int64_t)0 : (int64_t)wrap1(j, P.ny)) + (int64_t)P.ny * p);
 }
 
 
@@ -704,7 +700,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
             const int bc = k / G::FX, a = k - bc * G::FX, c = bc / G::FY, b = bc - c * G::FY;
             int l = t0z - 1 + c;
             l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
-            const int64_t o = near_cell(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+            const int64_t o = near_cell<TY == 1>(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
             for (int q = 0; q < 3; ++q) Fs[q * G::NF + k] = F6[q][o];
         }
@@ -713,7 +709,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
             const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
             int l = t0z - 1 + c;
             l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);
-            const int64_t o = near_cell(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+            const int64_t o = near_cell<TY == 1>(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
             for (int q = 0; q < 3; ++q) Bs[q * G::NE + k] = F6[3 + q][o];
         }
@@ -832,7 +828,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
             }
             const int l = t0z - 2 + z;
             if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
-            const int64_t o = near_cell(P, t0x - 2 + x, t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
+            const int64_t o = near_cell<TY == 1>(P, t0x - 2 + x, t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
             atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
         }
         __syncthreads();
