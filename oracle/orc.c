@@ -38,6 +38,7 @@
 #define M_E 9.1093837015e-31
 #define EPS0 8.8541878128e-12
 #define PI_D 3.14159265358979323846
+#define MP_OVER_ME 1836.15267343 /* proton / electron mass (CODATA 2018) */
 
 typedef struct {
     real *x[3], *u[3], *w;
@@ -56,7 +57,10 @@ struct orc_sim {
     real K, n0n, wbeam, B0;
     real *E[3], *B[3], *J[3];
     int64_t k0, step, sh_lo, sh_hi, beam_lost, plasma_removed;
-    orc_sp sp[2];
+    /* species 0 beam electrons, 1 plasma electrons, 2 mobile plasma ions
+     * (ions == 2): charge and mass in units of e and m_e */
+    orc_sp sp[3];
+    double q[3], m[3];
 };
 
 /* ------------------------------------------------------------------ */
@@ -367,7 +371,7 @@ void orc_deposit(orc_sim *s, const real X0[3], const real X1[3], real qw) {
  * ppc_x ppc_y on every node, so the ions' Esirkepov current is purely J_z and
  * depends on z only: the 1D running sum of -q w (S1 - S0) / dt per sheet. */
 void orc_ion_current(orc_sim *s, double t0, double t1, int32_t unit_weight) {
-    if (!s->c.ions) return;
+    if (s->c.ions != 1) return;
     int ptr = s->c.ppc[0] * s->c.ppc[1];
     for (int64_t l = s->sh_lo; l < s->sh_hi; ++l) {
         real w = sheet_weight(s, l);
@@ -485,29 +489,33 @@ static void sp_free(orc_sp *p) {
 }
 
 /* plasma sheet: nx ny ppc_x ppc_y cold electrons at rest in the lab
- * (u = -gR bR zhat in the boosted frame), order (j, b, i, a) */
+ * (u = -gR bR zhat in the boosted frame), order (j, b, i, a); with mobile
+ * ions, as many ions at the same places with the same velocity and weight
+ * (a neutral plasma, both populations on one lattice and one shape, sec. 1) */
 static void inject_sheet(orc_sim *s, int64_t l, double t) {
     real w = sheet_weight(s, l);
     if (RE(w) == 0.0) return;
     int px = s->c.ppc[0], py = s->c.ppc[1];
     int64_t add = (int64_t)s->nx * s->ny * px * py;
-    orc_sp *p = &s->sp[1];
-    sp_reserve(p, p->n + add);
     double z = sheet_z(s, l, t);
-    for (int j = 0; j < s->ny; ++j)
-        for (int bb = 0; bb < py; ++bb)
-            for (int i = 0; i < s->nx; ++i)
-                for (int aa = 0; aa < px; ++aa) {
-                    int64_t q = p->n++;
-                    p->x[0][q] = i + (aa + 0.5) / px;
-                    p->x[1][q] = j + (bb + 0.5) / py;
-                    p->x[2][q] = z;
-                    p->u[0][q] = 0.0;
-                    p->u[1][q] = 0.0;
-                    p->u[2][q] = -s->uR;
-                    p->w[q] = w;
-                    p->alive[q] = 1;
-                }
+    for (int sp = 1; sp <= (s->c.ions == 2 ? 2 : 1); ++sp) {
+        orc_sp *p = &s->sp[sp];
+        sp_reserve(p, p->n + add);
+        for (int j = 0; j < s->ny; ++j)
+            for (int bb = 0; bb < py; ++bb)
+                for (int i = 0; i < s->nx; ++i)
+                    for (int aa = 0; aa < px; ++aa) {
+                        int64_t q = p->n++;
+                        p->x[0][q] = i + (aa + 0.5) / px;
+                        p->x[1][q] = j + (bb + 0.5) / py;
+                        p->x[2][q] = z;
+                        p->u[0][q] = 0.0;
+                        p->u[1][q] = 0.0;
+                        p->u[2][q] = -s->uR;
+                        p->w[q] = w;
+                        p->alive[q] = 1;
+                    }
+    }
 }
 
 static double zlo_of(const orc_sim *s) { return (double)(s->k0 + 3); }
@@ -531,6 +539,10 @@ orc_sim *orc_new(const orc_config *c, const double *normals) {
     s->uR = s->gR * s->bR;
     s->nref = EPS0 * M_E * C_LIGHT * C_LIGHT / (Q_E * Q_E * D * D);
     s->zoff = c->zc_cells;
+    s->q[0] = s->q[1] = -1.0;
+    s->m[0] = s->m[1] = 1.0;
+    s->q[2] = 1.0;
+    s->m[2] = c->ion_mass > 0 ? c->ion_mass : MP_OVER_ME;
     for (int q = 0; q < 3; ++q) {
         s->E[q] = (real *)calloc(s->nc, sizeof(real));
         s->B[q] = (real *)calloc(s->nc, sizeof(real));
@@ -620,8 +632,7 @@ void orc_free(orc_sim *s) {
         free(s->B[q]);
         free(s->J[q]);
     }
-    sp_free(&s->sp[0]);
-    sp_free(&s->sp[1]);
+    for (int sp = 0; sp < 3; ++sp) sp_free(&s->sp[sp]);
     free(s);
 }
 
@@ -639,8 +650,9 @@ static void wrap_pos(const orc_sim *s, real X[3]) {
     }
 }
 
-/* gather + external field -> push -> move -> deposit for one particle */
-static void particle_update(orc_sim *s, orc_sp *p, int64_t q, double t) {
+/* gather + external field -> push -> move -> deposit for one particle of species sp */
+static void particle_update(orc_sim *s, int sp, int64_t q, double t) {
+    orc_sp *p = &s->sp[sp];
     real X[3] = {p->x[0][q], p->x[1][q], p->x[2][q]};
     real U[3] = {p->u[0][q], p->u[1][q], p->u[2][q]};
     real Ep[3], Bp[3], Ee[3], Be[3], Un[3], X1[3];
@@ -650,10 +662,10 @@ static void particle_update(orc_sim *s, orc_sp *p, int64_t q, double t) {
         Ep[d] += Ee[d];
         Bp[d] += Be[d];
     }
-    orc_push(s->c.pusher, -1.0, s->dt, U, Ep, Bp, Un);
+    orc_push(s->c.pusher, s->q[sp] / s->m[sp], s->dt, U, Ep, Bp, Un);
     real g = RSQRT(1.0 + dot3(Un, Un));
     for (int d = 0; d < 3; ++d) X1[d] = X[d] + s->dt * Un[d] / g;
-    orc_deposit(s, X, X1, -p->w[q]);
+    orc_deposit(s, X, X1, s->q[sp] * p->w[q]);
     wrap_pos(s, X1);
     for (int d = 0; d < 3; ++d) {
         p->x[d][q] = X1[d];
@@ -685,7 +697,7 @@ static int window_events(orc_sim *s, double t1) {
         shifted = 1;
     }
     double lo = zlo_of(s), hi = zhi_of(s);
-    for (int sp = 0; sp < 2; ++sp) {
+    for (int sp = 0; sp < 3; ++sp) {
         orc_sp *p = &s->sp[sp];
         for (int64_t q = 0; q < p->n; ++q)
             if (p->alive[q] && (RE(p->x[2][q]) < lo || RE(p->x[2][q]) >= hi)) {
@@ -711,10 +723,10 @@ static void step_once(orc_sim *s) {
     double t = s->step * s->dt, t1 = (s->step + 1) * s->dt;
     orc_b_half(s); /* B^n */
     orc_zero_J(s);
-    for (int sp = 0; sp < 2; ++sp) {
+    for (int sp = 0; sp < 3; ++sp) {
         orc_sp *p = &s->sp[sp];
         for (int64_t q = 0; q < p->n; ++q)
-            if (p->alive[q]) particle_update(s, p, q, t);
+            if (p->alive[q]) particle_update(s, sp, q, t);
     }
     orc_ion_current(s, t, t1, 0);
     orc_b_half(s); /* B^{n+1/2} */
@@ -752,6 +764,8 @@ void orc_info(const orc_sim *s, orc_info_t *o) {
     o->sheet_hi = s->sh_hi;
     o->beam_lost = s->beam_lost;
     o->plasma_removed = s->plasma_removed;
+    o->n_ions = s->sp[2].n;
+    o->ion_mass = s->m[2];
 }
 
 real *orc_field(orc_sim *s, int32_t which) {
@@ -774,7 +788,7 @@ int32_t *orc_alive(orc_sim *s, int32_t sp) { return s->sp[sp].alive; }
 /* ------------------------------------------------------------------ */
 void orc_rho(orc_sim *s, int32_t mask, real *rho) {
     memset(rho, 0, sizeof(real) * s->nc);
-    for (int sp = 0; sp < 2; ++sp) {
+    for (int sp = 0; sp < 3; ++sp) {
         if (!(mask & (1 << sp))) continue;
         orc_sp *p = &s->sp[sp];
         for (int64_t q = 0; q < p->n; ++q) {
@@ -786,12 +800,12 @@ void orc_rho(orc_sim *s, int32_t mask, real *rho) {
                 for (int b = 0; b < 3; ++b)
                     for (int c = 0; c < 3; ++c) {
                         int64_t i = lo[0] + a, j = lo[1] + b, k = lo[2] + c;
-                        rho[fidx(s, i, j, k)] += -p->w[q] * orc_shape(X[0] - (double)i) *
+                        rho[fidx(s, i, j, k)] += s->q[sp] * p->w[q] * orc_shape(X[0] - (double)i) *
                                                  orc_shape(X[1] - (double)j) * orc_shape(X[2] - (double)k);
                     }
         }
     }
-    if ((mask & 4) && s->c.ions) {
+    if ((mask & 4) && s->c.ions == 1) {
         double t = s->step * s->dt;
         int ptr = s->c.ppc[0] * s->c.ppc[1];
         for (int64_t l = s->sh_lo; l < s->sh_hi; ++l) {
@@ -880,12 +894,15 @@ void orc_diag(orc_sim *s, double kb, orc_diag_t *o) {
         o->b2_abs = sqrt(c2 * c2 + s2 * s2) / W;
         o->kin_beam = kin;
     }
-    orc_sp *pp = &s->sp[1];
-    double kp = 0;
-    for (int64_t q = 0; q < pp->n; ++q) {
-        if (!pp->alive[q]) continue;
-        double uu = RE(pp->u[0][q]) * RE(pp->u[0][q]) + RE(pp->u[1][q]) * RE(pp->u[1][q]) + RE(pp->u[2][q]) * RE(pp->u[2][q]);
-        kp += RE(pp->w[q]) * (sqrt(1.0 + uu) - 1.0);
+    double kp = 0; /* plasma electrons and mobile ions: m w (gamma - 1) */
+    for (int sp = 1; sp < 3; ++sp) {
+        orc_sp *pp = &s->sp[sp];
+        for (int64_t q = 0; q < pp->n; ++q) {
+            if (!pp->alive[q]) continue;
+            double uu = RE(pp->u[0][q]) * RE(pp->u[0][q]) + RE(pp->u[1][q]) * RE(pp->u[1][q]) +
+                        RE(pp->u[2][q]) * RE(pp->u[2][q]);
+            kp += s->m[sp] * RE(pp->w[q]) * (sqrt(1.0 + uu) - 1.0);
+        }
     }
     o->kin_plasma = kp;
     double fe = 0;
@@ -898,9 +915,13 @@ void orc_diag(orc_sim *s, double kb, orc_diag_t *o) {
 /* adjoint                                                              */
 /* ------------------------------------------------------------------ */
 /* state vector: [beam x,y,z,ux,uy,uz (n_beam each)] [plasma 6 x n_plasma] [E 3 x nc] [B 3 x nc] */
-int64_t orc_state_len(const orc_sim *s) { return 6 * (s->sp[0].n + s->sp[1].n) + 6 * s->nc; }
+int64_t orc_state_len(const orc_sim *s) {
+    if (s->c.ions == 2) die("adjoint state: mobile ions are not modelled");
+    return 6 * (s->sp[0].n + s->sp[1].n) + 6 * s->nc;
+}
 
 void orc_get_state(const orc_sim *s, real *v) {
+    if (s->c.ions == 2) die("adjoint state: mobile ions are not modelled");
     int64_t o = 0;
     for (int sp = 0; sp < 2; ++sp) {
         const orc_sp *p = &s->sp[sp];
@@ -912,6 +933,7 @@ void orc_get_state(const orc_sim *s, real *v) {
 }
 
 void orc_set_state(orc_sim *s, const real *v) {
+    if (s->c.ions == 2) die("adjoint state: mobile ions are not modelled");
     int64_t o = 0;
     for (int sp = 0; sp < 2; ++sp) {
         orc_sp *p = &s->sp[sp];
@@ -1295,6 +1317,7 @@ real orc_seed_bunching(orc_sim *s, double kb, real *lam) {
  * step.  Discrete events (window shift, removal, injection) are those the
  * forward step takes from state n.  The sim is left at state n. */
 void orc_adjoint_step(orc_sim *s, const real *lam_in, real *lam_out, real *gK_log, real *gn_log) {
+    if (s->c.ions == 2) die("adjoint: mobile ions are not modelled");
     orc_snap z0;
     snap_take(s, &z0);
     double t = s->step * s->dt, t1 = (s->step + 1) * s->dt, dt = s->dt;

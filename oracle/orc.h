@@ -16,7 +16,9 @@
  *     plasma density [Eq. Nnormi]; lab elements drift at -c beta_R [Eq. Vprime];
  *   - moving window, absorbing z faces, beam particles dropped outside the
  *     window, plasma entering at the front and leaving at the back, ion
- *     current computed directly [sec. 1, last paragraphs];
+ *     current computed directly [sec. 1, last paragraphs]: immobile ions as
+ *     rigid lattice sheets, or mobile ions as a species of their own on the
+ *     electrons' lattice with the same shape;
  *   - diagnostics (beam moments, bunching factor, Gauss residual);
  *   - the exact discrete adjoint of one step (not in the paper; used to pin
  *     gradients of the final bunching factor w.r.t. undulator K and density).
@@ -43,15 +45,18 @@ typedef struct {
     int64_t n_beam;
     double charge_C, gamma_lab, espread, sigma[3], emit[2], zc_cells;
     double n0_cm3, pl_z0_m, pl_len_m, pl_ramp_m; /* pl_len_m <= 0: uniform */
-    int32_t ppc[3], ions;
+    int32_t ppc[3], ions;          /* ions: 0 none, 1 immobile, 2 mobile (species 2, mass ion_mass) */
     int32_t und_kind, pusher;      /* und: 0 none 1 helical 2 planar; pusher: 0 Boris 1 Vay */
     double K, lu_m, und_z0_m, und_len_m, und_ramp_periods;
     double hK, hn0;                /* complex-step: imaginary parts added to K and n0 (cs build only) */
+    double ion_mass;               /* mobile ions: mass in electron masses (<= 0: the proton's) */
 } orc_config;
 
 typedef struct {
     double dt, gR, bR, uR, bw, nref_m3, wbeam, ku, B0, n0n, zoff, F_elong, sig_zlab;
     int64_t k0, step, n_beam, n_plasma, sheet_lo, sheet_hi, beam_lost, plasma_removed;
+    int64_t n_ions; /* mobile ion slots (n_plasma counts electron slots) */
+    double ion_mass;
 } orc_info_t;
 
 typedef struct {
@@ -72,7 +77,7 @@ void orc_diag(orc_sim *s, double kb, orc_diag_t *out);
 
 /* array access: which = 0..8 -> Ex Ey Ez Bx By Bz Jx Jy Jz (logical window order i + nx(j + ny l)) */
 real *orc_field(orc_sim *s, int32_t which);
-/* species 0 beam, 1 plasma; which 0..2 position, 3..5 momentum, 6 weight */
+/* species 0 beam, 1 plasma electrons, 2 mobile ions; which 0..2 position, 3..5 momentum, 6 weight */
 real *orc_particles(orc_sim *s, int32_t species, int32_t which);
 int32_t *orc_alive(orc_sim *s, int32_t species);
 
@@ -86,7 +91,7 @@ void orc_deposit(orc_sim *s, const real X0[3], const real X1[3], real qw); /* ad
 void orc_ion_current(orc_sim *s, double t0, double t1, int32_t unit_weight); /* adds ion J_z into J */
 void orc_b_half(orc_sim *s);
 void orc_e_update(orc_sim *s);
-void orc_rho(orc_sim *s, int32_t mask, real *rho);   /* mask: 1 beam, 2 plasma, 4 ions */
+void orc_rho(orc_sim *s, int32_t mask, real *rho);   /* mask: 1 beam, 2 plasma electrons, 4 ions */
 void orc_gauss(orc_sim *s, real *r);                 /* r = div E - rho on every node */
 void orc_zero_J(orc_sim *s);
 

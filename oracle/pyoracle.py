@@ -28,6 +28,7 @@ class Config(C.Structure):
         ("K", C.c_double), ("lu_m", C.c_double), ("und_z0_m", C.c_double), ("und_len_m", C.c_double),
         ("und_ramp_periods", C.c_double),
         ("hK", C.c_double), ("hn0", C.c_double),
+        ("ion_mass", C.c_double),
     ]
 
 
@@ -35,7 +36,8 @@ class Info(C.Structure):
     _fields_ = [(n, C.c_double) for n in
                 ("dt", "gR", "bR", "uR", "bw", "nref_m3", "wbeam", "ku", "B0", "n0n", "zoff", "F_elong", "sig_zlab")] + \
                [(n, C.c_int64) for n in
-                ("k0", "step", "n_beam", "n_plasma", "sheet_lo", "sheet_hi", "beam_lost", "plasma_removed")]
+                ("k0", "step", "n_beam", "n_plasma", "sheet_lo", "sheet_hi", "beam_lost", "plasma_removed",
+                 "n_ions")] + [("ion_mass", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -127,6 +129,7 @@ def make_config(w: dict, *, pusher: int | None = None, bc_z: int = 0, dt_overrid
     c.n0_cm3, c.pl_z0_m, c.pl_len_m, c.pl_ramp_m = p["n0_lab_cm3"], p["z_start_lab_m"], p["length_lab_m"], p["ramp_up_lab_m"]
     c.ppc[:] = p["ppc"]
     c.ions = p["ions"]
+    c.ion_mass = p.get("ion_mass", 0.0)
     c.und_kind = u["kind"]
     c.K, c.lu_m, c.und_z0_m, c.und_len_m, c.und_ramp_periods = (u["K"], u["period_lab_m"], u["z_start_lab_m"],
                                                                u["length_lab_m"], u["entrance_ramp_periods"])
@@ -207,9 +210,11 @@ class Sim:
         self.L.orc_b_half(self.h)
 
     def particles(self, species: int, view: bool = False) -> dict:
-        """Particle arrays of a species (0 beam, 1 plasma): copies, or writable
-        views valid while the simulation lives when ``view`` is set."""
-        n = self.info().n_beam if species == 0 else self.info().n_plasma
+        """Particle arrays of a species (0 beam, 1 plasma electrons, 2 mobile
+        ions): copies, or writable views valid while the simulation lives when
+        ``view`` is set."""
+        i = self.info()
+        n = (i.n_beam, i.n_plasma, i.n_ions)[species]
         out = {}
         for k, name in enumerate(("x", "y", "z", "ux", "uy", "uz", "w")):
             out[name] = self._view(self.L.orc_particles(self.h, species, k), n, self.dtype)
@@ -226,17 +231,24 @@ class Sim:
         self.L.orc_gauss(self.h, r.ctypes.data)
         return r.reshape(self.cfg.nz, self.cfg.ny, self.cfg.nx)
 
+    def _no_mobile_ions(self):
+        if self.cfg.ions == 2:
+            raise NotImplementedError("the oracle's adjoint does not model mobile ions")
+
     def state(self) -> np.ndarray:
+        self._no_mobile_ions()
         v = np.zeros(self.L.orc_state_len(self.h), self.dtype)
         self.L.orc_get_state(self.h, v.ctypes.data)
         return v
 
     def set_state(self, v: np.ndarray):
+        self._no_mobile_ions()
         v = np.ascontiguousarray(v, dtype=self.dtype)
         assert v.size == self.L.orc_state_len(self.h)
         self.L.orc_set_state(self.h, v.ctypes.data)
 
     def adjoint_step(self, lam_in: np.ndarray, n_out: int):
+        self._no_mobile_ions()
         lam_in = np.ascontiguousarray(lam_in, dtype=self.dtype)
         out = np.zeros(n_out, self.dtype)
         gK = np.zeros(1, self.dtype)
@@ -249,6 +261,8 @@ def grad_bunching(w: dict, normals: np.ndarray, nsteps: int, kb: float, **cfg_kw
     """(L, K dL/dK, n0 dL/dn0) from the oracle's stored-state adjoint."""
     L = lib(False)
     cfg = make_config(w, **cfg_kw)
+    if cfg.ions == 2:
+        raise NotImplementedError("the oracle's adjoint does not model mobile ions")
     nrm = np.ascontiguousarray(normals, dtype=np.float64)
     out = np.zeros(3)
     L.orc_grad_bunching(C.byref(cfg), nrm.ctypes.data, int(nsteps), float(kb), out.ctypes.data)

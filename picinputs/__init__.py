@@ -8,8 +8,8 @@ oracle take these numbers and derive everything themselves.
 
 Workloads
 ---------
-The five workloads are 3D stand-ins for the paper's 2D runs (Table 1 of the
-paper, cases V., Und., Pl., Pl.+Und.).  Their sizes come from the build's
+Workloads 0-4 are 3D stand-ins for the paper's 2D runs (Table 1 of the
+paper, cases V., Und., Pl., Pl.+Und.); workload 5 is a 2D (x-z) run.  Their sizes come from the build's
 hot-path specification; every choice the paper leaves open is recorded next
 to the field it fixes:
 
@@ -21,7 +21,10 @@ to the field it fixes:
 * 0.1 % rms energy spread, 1 um normalised emittance in x and y;
 * undulator period 20 boosted-frame cells, i.e. 20*gamma_R cells in the lab,
   entrance one lab period ahead of the beam head, two-period linear ramp;
-* plasma lattice (1,1,2) for 2 particles per cell and (1,2,2) for 4.
+* plasma lattice (1,1,2) for 2 particles per cell and (1,2,2) for 4;
+* ions: 1 = immobile lab ions (the default of every workload), 2 = mobile
+  ions on the electrons' lattice, of mass ``ion_mass`` electron masses
+  (0 = the proton's).
 
 Lab-frame longitudinal positions (undulator start, plasma start) are measured
 from the beam centre at lab time 0.
@@ -53,7 +56,7 @@ def _base(nx, ny, nz, gamma_r, n_beam, sigma, steps):
                  "rel_energy_spread_rms": 1e-3, "sigma_cells": [float(s) for s in sigma],
                  "emit_n_m": [1e-6, 1e-6], "z_center_cells": nz // 2, "seed": 0},
         "plasma": {"n0_lab_cm3": 0.0, "ppc": [1, 1, 2], "z_start_lab_m": 0.0,
-                   "length_lab_m": 0.0, "ramp_up_lab_m": 0.0, "ions": 0},
+                   "length_lab_m": 0.0, "ramp_up_lab_m": 0.0, "ions": 0, "ion_mass": 0.0},
         "undulator": {"kind": 0, "K": 0.0, "period_lab_m": 0.0, "z_start_lab_m": 0.0,
                       "length_lab_m": 0.0, "entrance_ramp_periods": 0.0},
         "steps": int(steps),
@@ -74,7 +77,7 @@ def _with_plasma(w, n0_cm3, ppc, uniform=True, z_start_m=0.0, length_m=0.0, ramp
     w["plasma"] = {"n0_lab_cm3": float(n0_cm3), "ppc": list(ppc),
                    "z_start_lab_m": float(z_start_m),
                    "length_lab_m": 0.0 if uniform else float(length_m),
-                   "ramp_up_lab_m": float(ramp_m), "ions": 1}
+                   "ramp_up_lab_m": float(ramp_m), "ions": 1, "ion_mass": 0.0}
     return w
 
 
