@@ -93,12 +93,23 @@ typedef struct {
  * gamma_R n0 (Eq. Nnormi).  Longitudinal lab profile: zero before z_start,
  * linear up-ramp over ramp_up, flat to z_start + length, zero after;
  * length <= 0 means uniform everywhere.  Lab positions are measured from the
- * beam centre at lab time 0.  ions = 1 adds immobile lab ions on the same
- * lattice (their current j_i = v_R rho_i is computed directly, section 1). */
+ * beam centre at lab time 0.  Ions (section 1 computes their current
+ * directly and gives them the electrons' weighting):
+ *   ions = 0  none;
+ *   ions = 1  immobile lab ions on the same lattice, a rigid background whose
+ *             current j_i = v_R rho_i is a 1D profile along z;
+ *   ions = 2  mobile ions of charge +e and mass ion_mass electron masses
+ *             (0: the proton's), loaded with every sheet at the electrons'
+ *             places with their velocity and weight, pushed with q/m = +1/M
+ *             and deposited with the same shape.  They are stored among the
+ *             plasma particles with a negated weight (pic_read
+ *             returns them so); the adjoint refuses them (PIC_EINVAL).
+ * ion_mass must be finite and >= 0 (PIC_EINVAL otherwise). */
 typedef struct {
     double n0_lab_cm3;
     int32_t ppc[3], ions;
     double z_start_lab_m, length_lab_m, ramp_up_lab_m;
+    double ion_mass;
 } pic_plasma;
 
 /* Ideal undulator in the lab: B = B0 env (cos phi, sin phi, 0) (helical) or
@@ -193,7 +204,9 @@ PIC_API pic_status pic_step(pic_ctx *c, int32_t nsteps);
  * sum w at k = 2 pi / bunch_period_cells and 2k (boosted frame, fixed t').
  * Gauss: r = div E - rho on nodes at least 8 planes from the z faces; reports
  * max |r| and max |r - r_prev| against the previous Gauss call (planes aligned
- * by the window shift).  All sums in FP64. */
+ * by the window shift).  n_plasma counts plasma electrons and mobile ions;
+ * kin_plasma sums m w (gamma - 1) over both, m = 1 or ion_mass.  All sums in
+ * FP64. */
 enum { PIC_DIAG_MOMENTS = 1, PIC_DIAG_BUNCHING = 2, PIC_DIAG_ENERGY = 4, PIC_DIAG_GAUSS = 8 };
 typedef struct {
     double t, step, k0, n_beam, n_plasma, beam_lost, wsum;

@@ -39,7 +39,8 @@ class pic_beam(C.Structure):
 
 class pic_plasma(C.Structure):
     _fields_ = [("n0_lab_cm3", C.c_double), ("ppc", C.c_int32 * 3), ("ions", C.c_int32),
-                ("z_start_lab_m", C.c_double), ("length_lab_m", C.c_double), ("ramp_up_lab_m", C.c_double)]
+                ("z_start_lab_m", C.c_double), ("length_lab_m", C.c_double), ("ramp_up_lab_m", C.c_double),
+                ("ion_mass", C.c_double)]
 
 
 class pic_undulator(C.Structure):
@@ -157,6 +158,7 @@ def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHE
     plasma.n0_lab_cm3 = p["n0_lab_cm3"]
     plasma.ppc[:] = p["ppc"]
     plasma.ions = p["ions"]
+    plasma.ion_mass = p.get("ion_mass", 0.0)
     plasma.z_start_lab_m, plasma.length_lab_m, plasma.ramp_up_lab_m = (p["z_start_lab_m"], p["length_lab_m"],
                                                                        p["ramp_up_lab_m"])
     und = pic_undulator(u["kind"], 0, u["K"], u["period_lab_m"], u["z_start_lab_m"], u["length_lab_m"],

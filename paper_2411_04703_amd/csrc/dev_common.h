@@ -17,7 +17,7 @@ struct Params {
     int und_kind, pusher;
     double ku, z0u, Lu, Ru, B0;
     // plasma (lab cells)
-    int has_plasma, ions, ppx, ppy, ppz, pad0;
+    int has_plasma, ions, ppx, ppy, ppz, mobile;  // ions: immobile lab ions; mobile: ions as particles
     double n0n, z0p, Lp, Rp, wsheet; // wsheet = gR n0n / (ppx ppy ppz)
     double wbeam;
     double gthr;                // FP32 mode: FP64 push above this gamma
@@ -26,6 +26,8 @@ struct Params {
     int tx, ty, tz, ntx, nty, ntz, nbins, pad2;
     // FP32 mode: packed cell = i | j << cbx | l << (cbx + cby); tile edges 2^lgx, 2^lgy, 2^lgz
     int cbx, cby, lgx, lgy, lgz, pad3;
+    // mobile ions: mass in electron masses, and the pusher's half-step factor 0.5 (q/m) dt = 0.5 dt / mi
+    double mi, ahi;
 };
 
 // Window position during one step (host-decided, deterministic from the step count).
@@ -157,7 +159,8 @@ __device__ inline void ext_field64(const Params &P, double z, double t, double E
     dB[1] = P.gR * P.gR * dby;
 }
 
-// ---------------------------------------------------------------- pushers (q/m = -1)
+// ---------------------------------------------------------------- pushers
+// a = (q/m) dt / 2: -dt/2 for electrons, +dt / (2 M) for mobile ions of mass M
 template <typename T> __device__ inline T dot3(const T a[3], const T b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 template <typename T> __device__ inline void cross3(const T a[3], const T b[3], T o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];
@@ -166,8 +169,7 @@ template <typename T> __device__ inline void cross3(const T a[3], const T b[3], 
 }
 
 // Boris: half kick, rotation, half kick.
-template <typename T> __device__ inline void push_boris(T dt, const T u[3], const T E[3], const T B[3], T out[3]) {
-    T a = T(-0.5) * dt;
+template <typename T> __device__ inline void push_boris(T a, const T u[3], const T E[3], const T B[3], T out[3]) {
     T um[3], Tv[3], S[3], up[3], c[3];
     for (int d = 0; d < 3; ++d) um[d] = u[d] + a * E[d];
     T gm = sqrt(T(1) + dot3(um, um));
@@ -181,8 +183,7 @@ template <typename T> __device__ inline void push_boris(T dt, const T u[3], cons
 }
 
 // Vay: velocity average in the magnetic term, closed-form Lorentz factor.
-template <typename T> __device__ inline void push_vay(T dt, const T u[3], const T E[3], const T B[3], T out[3]) {
-    T a = T(-0.5) * dt;
+template <typename T> __device__ inline void push_vay(T a, const T u[3], const T E[3], const T B[3], T out[3]) {
     T g0 = sqrt(T(1) + dot3(u, u));
     T v0[3], c[3], u1[3], tau[3], t[3];
     for (int d = 0; d < 3; ++d) v0[d] = u[d] / g0;
@@ -200,11 +201,11 @@ template <typename T> __device__ inline void push_vay(T dt, const T u[3], const 
     for (int d = 0; d < 3; ++d) out[d] = sf * (u1[d] + ut * t[d] + c[d]);
 }
 
-template <typename T> __device__ inline void push(int pusher, T dt, const T u[3], const T E[3], const T B[3], T out[3]) {
+template <typename T> __device__ inline void push(int pusher, T a, const T u[3], const T E[3], const T B[3], T out[3]) {
     if (pusher == 1)
-        push_vay(dt, u, E, B, out);
+        push_vay(a, u, E, B, out);
     else
-        push_boris(dt, u, E, B, out);
+        push_boris(a, u, E, B, out);
 }
 
 // plasma lab profile in [0, 1] (linear up-ramp, flat, zero outside; Lp <= 0: uniform)
@@ -219,6 +220,12 @@ __host__ __device__ inline double plasma_profile(double Lp, double z0p, double R
 // boosted position of lattice sheet l at time t: ((l + 1/2) / ppz) - bR t
 __host__ __device__ inline double sheet_z(int64_t l, int ppz, double bR, double t) {
     return ((double)l + 0.5) / ppz - bR * t;
+}
+
+// particles of one lattice sheet: nx ny ppx ppy electrons, then as many mobile
+// ions at the same places (stored with the plasma, marked by a negative weight)
+__host__ __device__ inline int64_t sheet_particles(const Params &P) {
+    return (int64_t)P.plane * P.ppx * P.ppy * (P.mobile ? 2 : 1);
 }
 
 // per-particle weight of sheet l (boosted density gR n(z_lab), Eq. Nnormi)

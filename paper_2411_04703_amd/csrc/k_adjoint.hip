@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(AT) k_adj_particles(Params P, StepCtx S, Part6
                 B[d] += Be[d];
             }
             double Un[3];
-            push<double>(P.pusher, P.dt, U, E, B, Un);
+            push<double>(P.pusher, -0.5 * P.dt, U, E, B, Un);
             double g = sqrt(1.0 + dot3(Un, Un));
             double X1[3];
             for (int d = 0; d < 3; ++d) X1[d] = X[d] + P.dt * Un[d] / g;

@@ -86,14 +86,16 @@ __global__ void __launch_bounds__(DT) k_mom2(Part64 p, int64_t n, double wconst,
     block_sum<8>(s, v, out);
 }
 
-__global__ void __launch_bounds__(DT) k_kin(Part64 p, int64_t n, double *out) {
+// count and kinetic energy m w (gamma - 1) of the plasma slots (mobile ions: w < 0, mass mi)
+__global__ void __launch_bounds__(DT) k_kin(Part64 p, int64_t n, double mi, double *out) {
     __shared__ double s[2][DT];
     double v[2] = {0, 0};
     int64_t q = (int64_t)blockIdx.x * DT + threadIdx.x;
     if (q < n && p.alive[q]) {
         double ux = p.ux[q], uy = p.uy[q], uz = p.uz[q];
         v[0] = 1.0;
-        v[1] = p.w[q] * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        const double w = p.w[q];
+        v[1] = (w < 0.0 ? -mi * w : w) * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
     }
     block_sum<2>(s, v, out);
 }
@@ -109,7 +111,7 @@ template <typename T> __global__ void __launch_bounds__(DT) k_fenergy(FieldsT<T>
     block_sum<1>(s, v, out);
 }
 
-// charge of FP64 particles on the nodes (q = -1), FP64 atomics into rho (ring order)
+// charge -w of FP64 particles on the nodes (mobile ions carry w < 0), FP64 atomics into rho (ring order)
 __global__ void __launch_bounds__(DT) k_rho64(Params P, int64_t k0, int k0r, Part64 p, int64_t n, double *rho) {
     int64_t q = (int64_t)blockIdx.x * DT + threadIdx.x;
     if (q >= n || !p.alive[q]) return;
@@ -355,7 +357,7 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
         if (c.precision == PIC_FP64_PLAIN) {
             if (c.np_slots > 0) {
                 int nblk = nblocks(c.np_slots, DT);
-                hipLaunchKernelGGL(k_kin, dim3(nblk), dim3(DT), 0, c.st, c.p64, c.np_slots, c.red);
+                hipLaunchKernelGGL(k_kin, dim3(nblk), dim3(DT), 0, c.st, c.p64, c.np_slots, c.P.mi, c.red);
                 std::vector<double> kp;
                 host_sum(c, nblk, 2, kp);
                 o->n_plasma = kp[0];

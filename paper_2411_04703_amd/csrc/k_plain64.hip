@@ -75,13 +75,18 @@ void launch_beam_init64(const Params &P, const double *normals, int64_t n, const
 // ---------------------------------------------------------------- plasma sheets
 // Cold lattice electrons at rest in the lab: boosted u = -gR bR zhat, boosted
 // density gR n (Eq. Nnormi).  Sheet l holds nx ny ppx ppy particles in the
-// order (j, b, i, a), x = i + (a + 1/2)/ppx, y = j + (b + 1/2)/ppy.
+// order (j, b, i, a), x = i + (a + 1/2)/ppx, y = j + (b + 1/2)/ppy; with
+// mobile ions, as many ions follow in the same order, with the same velocity
+// and the weight negated (the charge sign: the deposit and the charge density
+// take -w, and the push selects q/m = +1/M by it).
 __global__ void k_inject64(Params P, int64_t l0, int64_t total, double t, Part64 p, int64_t slot0) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
-    int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
+    const int64_t per = sheet_particles(P), pe = (int64_t)P.plane * P.ppx * P.ppy;
     int64_t l = l0 + q / per;
     int64_t r = q % per;
+    const bool ion = r >= pe;
+    if (ion) r -= pe;
     int a = (int)(r % P.ppx);
     r /= P.ppx;
     int i = (int)(r % P.nx);
@@ -95,13 +100,13 @@ __global__ void k_inject64(Params P, int64_t l0, int64_t total, double t, Part64
     p.ux[s] = 0.0;
     p.uy[s] = 0.0;
     p.uz[s] = -P.uR;
-    p.w[s] = sheet_weight(P, l);
+    p.w[s] = ion ? -sheet_weight(P, l) : sheet_weight(P, l);
     p.alive[s] = 1;
 }
 
 void launch_inject64(const Params &P, int64_t l0, int64_t nsheets, double t, Part64 p, int64_t slot0,
                      hipStream_t st) {
-    int64_t total = nsheets * (int64_t)P.plane * P.ppx * P.ppy;
+    int64_t total = nsheets * sheet_particles(P);
     if (total <= 0) return;
     hipLaunchKernelGGL(k_inject64, dim3(nblocks(total, 256)), dim3(256), 0, st, P, l0, total, t, p, slot0);
 }
@@ -137,7 +142,8 @@ __device__ inline double gather64(const Params &P, const StepCtx &S, const doubl
 // quadratic shapes, on the tight four-node window of each axis:
 //   W_c = DS_c (S0_a S0_b + DS_a S0_b / 2 + S0_a DS_b / 2 + DS_a DS_b / 3),
 //   J_c(m + 1/2) = J_c(m - 1/2) - q w W_c(m) / dt (running sum from below),
-// the fourth running sum vanishing identically.  q = -1 (electrons).
+// the fourth running sum vanishing identically.  q w = -w: electrons carry
+// w > 0, mobile ions w < 0.
 __device__ inline void deposit64(const Params &P, const StepCtx &S, double *J[3], const double X0[3],
                                  const double X1[3], double w) {
     double S0[3][4], DS[3][4];
@@ -193,7 +199,7 @@ __global__ void __launch_bounds__(256) k_step64(Params P, StepCtx S, Part64 p, i
         B[d] += Be[d];
     }
     double Un[3];
-    push<double>(P.pusher, P.dt, U, E, B, Un);
+    push<double>(P.pusher, p.w[q] < 0.0 ? P.ahi : -0.5 * P.dt, U, E, B, Un);
     double g = sqrt(1.0 + dot3(Un, Un));
     double X1[3];
     for (int d = 0; d < 3; ++d) X1[d] = X[d] + P.dt * Un[d] / g;

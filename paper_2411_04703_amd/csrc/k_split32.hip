@@ -323,16 +323,17 @@ __device__ inline void ext32(const Params &P, double a_l, float cphi, float sphi
     B[1] += g * by;
 }
 
-// push in FP32, or FP64 above the Lorentz-factor threshold; false when non-finite
-__device__ inline bool push32(const Params &P, const float E[3], const float B[3], float u[3]) {
+// push in FP32, or FP64 above the Lorentz-factor threshold; false when non-finite.
+// ion: a mobile ion (q/m = +1/M), else an electron (q/m = -1)
+__device__ inline bool push32(const Params &P, bool ion, const float E[3], const float B[3], float u[3]) {
     float g2 = 1.0f + u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     float un[3];
     if (g2 > (float)(P.gthr * P.gthr)) {
         double ud[3] = {u[0], u[1], u[2]}, Ed[3] = {E[0], E[1], E[2]}, Bd[3] = {B[0], B[1], B[2]}, o[3];
-        push<double>(P.pusher, P.dt, ud, Ed, Bd, o);
+        push<double>(P.pusher, ion ? P.ahi : -0.5 * P.dt, ud, Ed, Bd, o);
         for (int d = 0; d < 3; ++d) un[d] = (float)o[d];
     } else {
-        push<float>(P.pusher, (float)P.dt, u, E, B, un);
+        push<float>(P.pusher, ion ? (float)P.ahi : -0.5f * (float)P.dt, u, E, B, un);
     }
     for (int d = 0; d < 3; ++d) u[d] = un[d];
     return isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]);
@@ -571,7 +572,7 @@ __device__ inline bool advance(const Params &P, float EB[6], bool ext, double a_
                                float X1[3]) {
     float E[3] = {EB[0], EB[1], EB[2]}, B[3] = {EB[3], EB[4], EB[5]};
     if (ext) ext32(P, a_l, cphi, sphi, q.o[2], E, B);
-    if (!push32(P, E, B, q.u)) return false;
+    if (!push32(P, q.w < 0.0f, E, B, q.u)) return false;
     float ig = 1.0f / sqrtf(1.0f + q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
     const float dt = (float)P.dt;
     for (int d = 0; d < 3; ++d) X1[d] = q.o[d] + dt * (q.u[d] * ig);
@@ -1214,9 +1215,11 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
     PState s;
     int key = 0;
     if (act) {
-        int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
+        const int64_t per = sheet_particles(P), pe = (int64_t)P.plane * P.ppx * P.ppy;
         int64_t l = l0 + q / per;
         int64_t r = q % per;
+        const bool ion = r >= pe;  // mobile ions follow the sheet's electrons, weight negated
+        if (ion) r -= pe;
         int a = (int)(r % P.ppx);
         r /= P.ppx;
         s.i = (int)(r % P.nx);
@@ -1234,7 +1237,7 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
         s.u[0] = 0.0f;
         s.u[1] = 0.0f;
         s.u[2] = (float)(-P.uR);
-        s.w = (float)w;
+        s.w = ion ? (float)-w : (float)w;
         s.id = (int)(id0 + q);  // the lattice particle's FP64 record slot
         act = w != 0.0 && s.l >= 3 && s.l < P.nz - 4;
         key = act ? bin_of(P, s.i, s.j, s.l) : 0;
@@ -1364,7 +1367,7 @@ void split_beam_init(Ctx &c, const double *normals_dev) {
 static pic_status inject_runs32(Ctx &c, int64_t l0, int64_t l1, double t, int64_t k0, const OutStore &o,
                                 int32_t *o_id, int bins) {
     const Params &P = c.P;
-    const int64_t per = (int64_t)P.plane * P.ppx * P.ppy;
+    const int64_t per = sheet_particles(P);
     int64_t l = l0;
     while (l < l1) {
         while (l < l1 && sheet_weight(P, l) == 0.0) ++l;
@@ -1637,7 +1640,7 @@ __global__ void k_split_out(Params P, int64_t k0, Part32 in, const int64_t *off,
     }
 }
 
-// charge of split particles on the nodes (q = -1), FP64 atomics into rho (ring order)
+// charge -w of split particles on the nodes (mobile ions carry w < 0), FP64 atomics into rho (ring order)
 __global__ void k_split_rho(Params P, int64_t k0, int k0r, Part32 in, const int64_t *off, const int32_t *cnt,
                             int64_t ovf_start, int32_t ovf_n, int nbins, double *rho) {
     int b = blockIdx.x;
@@ -1691,7 +1694,8 @@ __global__ void k_split_kin(Params P, Part32 in, const int64_t *off, const int32
         int64_t q = s0 + k;
         double ux = in.ux[q], uy = in.uy[q], uz = in.uz[q];
         v0 += 1.0;
-        v1 += (double)in.w[q] * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
+        const double w = (double)in.w[q];
+        v1 += (w < 0.0 ? -P.mi * w : w) * (sqrt(1.0 + ux * ux + uy * uy + uz * uz) - 1.0);
     }
     s[0][threadIdx.x] = v0;
     s[1][threadIdx.x] = v1;

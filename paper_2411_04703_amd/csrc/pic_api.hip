@@ -15,7 +15,8 @@ namespace pic {
 
 // CODATA 2018
 static const double kC = 299792458.0, kQe = 1.602176634e-19, kMe = 9.1093837015e-31,
-                    kEps0 = 8.8541878128e-12, kPi = 3.14159265358979323846;
+                    kEps0 = 8.8541878128e-12, kPi = 3.14159265358979323846,
+                    kProtonMass = 1836.15267343;  // proton / electron mass
 
 pic_status hip_check(Ctx &c, hipError_t e, const char *what) {
     char buf[512];
@@ -63,6 +64,9 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (p->n0_lab_cm3 < 0) return fail(err, PIC_EINVAL, "plasma: n0 >= 0");
     if (p->n0_lab_cm3 > 0 && (p->ppc[0] < 1 || p->ppc[1] < 1 || p->ppc[2] < 1))
         return fail(err, PIC_EINVAL, "plasma: ppc >= 1");
+    if (p->ions < 0 || p->ions > 2) return fail(err, PIC_EINVAL, "plasma: ions is 0 (none), 1 (immobile) or 2 (mobile)");
+    if (!(p->ion_mass >= 0.0) || std::isinf(p->ion_mass))
+        return fail(err, PIC_EINVAL, "plasma: ion_mass >= 0 (0: the proton's)");
     if (u->kind < 0 || u->kind > 2) return fail(err, PIC_EINVAL, "undulator: kind 0, 1 or 2");
     if (u->kind != 0 && !(u->period_lab_m > 0)) return fail(err, PIC_EINVAL, "undulator: period > 0");
     if (o->precision != PIC_FP64_PLAIN && o->precision != PIC_FP32_SPLIT)
@@ -100,7 +104,10 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
         P.B0 = u->K * P.ku;
     }
     P.has_plasma = p->n0_lab_cm3 > 0;
-    P.ions = P.has_plasma && p->ions;
+    P.ions = P.has_plasma && p->ions == 1;
+    P.mobile = P.has_plasma && p->ions == 2;
+    P.mi = p->ion_mass > 0 ? p->ion_mass : kProtonMass;
+    P.ahi = 0.5 * P.dt / P.mi;
     P.ppx = std::max(1, p->ppc[0]);
     P.ppy = std::max(1, p->ppc[1]);
     P.ppz = std::max(1, p->ppc[2]);
@@ -207,7 +214,7 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
     pl.precision = o->precision;
     pl.record = o->record;
     pl.check_every = o->check_every > 0 ? o->check_every : 64;
-    int64_t sheet = (int64_t)P.plane * P.ppx * P.ppy;
+    int64_t sheet = sheet_particles(P);
     int64_t fill = P.has_plasma ? (int64_t)P.nz * P.ppz * sheet : 0;
     int64_t maxs = o->max_steps > 0 ? o->max_steps : 0;
     pl.cap_b = b->n_macro;
@@ -310,7 +317,7 @@ StepCtx make_step_ctx(const Ctx &c) {
 
 // inject the nonzero-weight sheets of [l0, l1) at time t (FP64 mode slots)
 static pic_status inject_range64(Ctx &c, int64_t l0, int64_t l1, double t) {
-    int64_t sheet = (int64_t)c.P.plane * c.P.ppx * c.P.ppy;
+    int64_t sheet = sheet_particles(c.P);
     int64_t l = l0;
     while (l < l1) {
         while (l < l1 && sheet_weight(c.P, l) == 0.0) ++l;
@@ -416,7 +423,7 @@ static pic_status step64(Ctx &c) {
     pic_status s = end_of_step_sheets(c, S);
     timing_end(c, 2, t4);
     if (s != PIC_OK) return s;
-    if (!c.record && c.P.has_plasma && (c.step % c.check_every == 0 || c.cap_p - c.np_slots < 4 * sheets_per_step(P) * (int64_t)P.plane * P.ppx * P.ppy)) {
+    if (!c.record && c.P.has_plasma && (c.step % c.check_every == 0 || c.cap_p - c.np_slots < 4 * sheets_per_step(P) * sheet_particles(P))) {
         int64_t n = compact64(c, c.p64, c.p64alt, c.np_slots);
         std::swap(c.p64, c.p64alt);
         c.np_slots = n;
@@ -886,6 +893,10 @@ pic_status pic_adjoint_seed_bunching(pic_ctx *c, double bunch_period_cells, void
         c->err = "adjoint needs FP64 mode with record = 1";
         return PIC_ESTATE;
     }
+    if (c->P.mobile) {
+        c->err = "adjoint: mobile ions are not supported";
+        return PIC_EINVAL;
+    }
     double kb = bunch_period_cells > 0 ? 2.0 * kPi / bunch_period_cells : c->k_bunch_default;
     return adjoint_seed(*c, kb, (double *)lam, loss);
 }
@@ -895,6 +906,10 @@ pic_status pic_adjoint_step(pic_ctx *c, void *lam, double grad[2]) {
     if (!c->record || c->precision != PIC_FP64_PLAIN) {
         c->err = "adjoint needs FP64 mode with record = 1";
         return PIC_ESTATE;
+    }
+    if (c->P.mobile) {
+        c->err = "adjoint: mobile ions are not supported";
+        return PIC_EINVAL;
     }
     return adjoint_step(*c, (double *)lam, grad);
 }

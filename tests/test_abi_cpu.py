@@ -91,6 +91,9 @@ def test_layout_scales_with_capacity():
     (lambda w: w["undulator"].update(kind=1, period_lab_m=0.0), abi.PIC_EINVAL),
     (lambda w: w["plasma"].update(n0_lab_cm3=1e16, ppc=[0, 1, 2]), abi.PIC_EINVAL),
     (lambda w: w["beam"].update(sigma_cells=[0.0, 1.0, 1.0]), abi.PIC_EINVAL),
+    (lambda w: w["plasma"].update(n0_lab_cm3=1e16, ions=3), abi.PIC_EINVAL),
+    (lambda w: w["plasma"].update(n0_lab_cm3=1e16, ions=2, ion_mass=-1.0), abi.PIC_EINVAL),
+    (lambda w: w["plasma"].update(n0_lab_cm3=1e16, ions=2, ion_mass=float("nan")), abi.PIC_EINVAL),
 ])
 def test_invalid_configurations_are_rejected(mutate, expect):
     w = pin.workload(0)
@@ -144,3 +147,16 @@ def test_gpu_entry_points_fail_loudly_without_device():
     w = pin.scaled(pin.workload(0), n_beam=16)
     with pytest.raises(RuntimeError):
         sim.Sim(w, pin.beam_normals(16))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mobile_ions_double_the_plasma_capacity(precision):
+    w = pin.workload(1)
+    a = sim.query_layout(w, precision=precision)
+    w["plasma"].update(ions=2, ion_mass=0.0)
+    b = sim.query_layout(w, precision=precision)
+    if precision == 0:
+        assert b.plasma_capacity == 2 * a.plasma_capacity
+    else:  # the FP32 bins add a fixed slack per bin
+        assert 1.95 * a.plasma_capacity < b.plasma_capacity <= 2 * a.plasma_capacity
+    assert b.arena_bytes > a.arena_bytes

@@ -72,6 +72,16 @@ def _case(name):
         w["undulator"]["kind"] = 2
         w["beam"]["charge_C"] = 3e-10
         return w
+    if name == "mobile_ions":  # ions as particles (protons), pushed and deposited like the electrons
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=8192, sigma=(2, 2, 8))
+        w["plasma"].update(ions=2, ion_mass=0.0)
+        w["beam"]["charge_C"] = 3e-9
+        return w
+    if name == "light_ions":  # mass 4 ions: a strong ion response within a few steps
+        w = pin.scaled(pin.workload(1), nx=16, ny=16, nz=64, n_beam=4096, sigma=(2, 2, 8))
+        w["plasma"].update(ions=2, ion_mass=4.0)
+        w["beam"]["charge_C"] = 3e-9
+        return w
     if name == "ragged":  # non-power-of-two grid of 3 x 5 x 4 tiles (8 x 8 x 16), beam count not a multiple of 64
         w = pin.scaled(pin.workload(1), nx=24, ny=40, nz=64, n_beam=4099, sigma=(2, 3, 8))
         w["beam"]["charge_C"] = 3e-9
@@ -80,7 +90,8 @@ def _case(name):
 
 
 CASES = ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "ramp_channel", "plasma_only", "beam_only",
-         "static_window", "no_boost", "ragged", "planar_undulator", "plane_2d", "planar_2d"]
+         "static_window", "no_boost", "ragged", "planar_undulator", "plane_2d", "planar_2d", "mobile_ions",
+         "light_ions"]
 
 
 def _pair(w, seed=0, **opts):
@@ -112,8 +123,15 @@ def _compare(ref, gpu, tol, what=""):
         a, b = gpu.field(f), ref.field(f)
         scale = max(np.linalg.norm(b), gross, 1e-30)
         assert np.linalg.norm(a - b) <= tol * scale + 1e-300, (what, f, _rel(a, b))
-    for sp in (0, 1):
-        g, o = gpu.particles(sp), ref.particles(sp)
+    pairs = [(gpu.particles(0), ref.particles(0)), (gpu.particles(1), ref.particles(1))]
+    if ref.info().n_ions:
+        # mobile ions share the GPU's plasma slots (after the electrons of each sheet), weight negated
+        g = pairs[1][0]
+        ion = g["w"] < 0
+        gi = {k: v[ion] for k, v in g.items()}
+        gi["w"] = -gi["w"]
+        pairs = [pairs[0], ({k: v[~ion] for k, v in g.items()}, pairs[1][1]), (gi, ref.particles(2))]
+    for sp, (g, o) in enumerate(pairs):
         ag, ao = g["alive"] == 1, o["alive"] == 1
         assert ag.sum() == ao.sum(), (what, sp, ag.sum(), ao.sum())
         if ao.sum() == 0:
