@@ -18,13 +18,16 @@ import time
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--workload", type=int, default=1, help="synthetic workload 0-4")
+    ap.add_argument("--workload", type=int, default=1, help="synthetic workload 0-5")
     ap.add_argument("--steps", type=int, default=None, help="steps (default: the workload's)")
     ap.add_argument("--every", type=int, default=100, help="report interval in steps")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-gauss", action="store_true", help="skip the FP64 Gauss-law residual (a full-grid pass)")
     ap.add_argument("--init-fields", action="store_true", help="start from the beam's self-field (else zero fields)")
+    ap.add_argument("--mobile-ions", type=float, default=None, metavar="MASS",
+                    help="plasma ions as particles of this mass in electron masses (0: the proton's); "
+                         "default: immobile ions")
     a = ap.parse_args(argv)
 
     import torch
@@ -34,6 +37,8 @@ def main(argv=None):
     from .sim import Sim
 
     w = pin.workload(a.workload)
+    if a.mobile_ions is not None and w["plasma"]["n0_lab_cm3"] > 0:
+        w["plasma"].update(ions=2, ion_mass=a.mobile_ions)
     steps = a.steps if a.steps is not None else w["steps"]
     prec = abi.PIC_FP32_SPLIT if a.precision == "fp32" else abi.PIC_FP64_PLAIN
     opts = {} if prec == abi.PIC_FP32_SPLIT else {"max_steps": max(64, a.every)}
