@@ -74,7 +74,7 @@ def test_fp32_init_matches_fp64(case):
 
 @pytest.mark.parametrize("case", ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "plasma_only", "beam_only",
                                   "static_window", "no_boost", "ragged", "planar_undulator", "plane_2d",
-                                  "planar_2d", "mobile_ions", "light_ions"])
+                                  "planar_2d", "mobile_ions", "light_ions", "ions_2d"])
 def test_fp32_steps_track_fp64(case):
     ref, s32, s64, w, _ = _sims(_w(case))
     for n in (1, 5, 20):

@@ -82,6 +82,10 @@ def _case(name):
         w["plasma"].update(ions=2, ion_mass=4.0)
         w["beam"]["charge_C"] = 3e-9
         return w
+    if name == "ions_2d":  # mobile ions (M = 4) on the x-z grid
+        w = _case("plane_2d")
+        w["plasma"].update(ions=2, ion_mass=4.0)
+        return w
     if name == "ragged":  # non-power-of-two grid of 3 x 5 x 4 tiles (8 x 8 x 16), beam count not a multiple of 64
         w = pin.scaled(pin.workload(1), nx=24, ny=40, nz=64, n_beam=4099, sigma=(2, 3, 8))
         w["beam"]["charge_C"] = 3e-9
@@ -91,7 +95,7 @@ def _case(name):
 
 CASES = ["undulator_beam", "beam_plasma_ions", "adjoint_sub", "ramp_channel", "plasma_only", "beam_only",
          "static_window", "no_boost", "ragged", "planar_undulator", "plane_2d", "planar_2d", "mobile_ions",
-         "light_ions"]
+         "light_ions", "ions_2d"]
 
 
 def _pair(w, seed=0, **opts):
