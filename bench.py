@@ -289,6 +289,7 @@ def main():
                    "precision": "fp32_split_fixed_point" if prec == abi.PIC_FP32_SPLIT else "fp64_plain",
                    "deposit_variant": args.variant, "tile": tile_used, "wg_per_cu": args.wg_per_cu},
         "fdtd_cell_updates_per_s": n_cells / (fdtd_ms * 1e-3) if fdtd_ms > 0 else None,
+        "cell_updates_per_s_whole_step": n_cells * steps / wall,
         "phase_ms_per_step": {"particles": part_ms, "fdtd": fdtd_ms, "window_ion_inject_sort": ms[2] / steps,
                               "step_events": ms[3] / steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
