@@ -11,7 +11,9 @@
 // back face, and at the front face while the window is at rest; a moving
 // window's front face keeps its tangential E, and the half planes beyond it
 // stay zero.
-// One thread per cell, x fastest: every array access is coalesced along x.
+// One thread per cell, x fastest: every array access is coalesced along x.  The
+// grid is (cells of a plane, ring planes): the ring plane is the block's y
+// index and (i, j) come from 32-bit arithmetic on the in-plane index.
 #include "pic_internal.h"
 
 namespace pic {
@@ -20,14 +22,21 @@ template <typename JT> __device__ inline double jvalue(JT v, double finv);
 template <> __device__ inline double jvalue<double>(double v, double) { return v; }
 template <> __device__ inline double jvalue<long long>(long long v, double finv) { return (double)v * finv; }
 
+// in-plane index s = i + nx j of the calling thread, false past the plane's end
+__device__ inline bool plane_cell(const Params &P, int &i, int &j) {
+    const int s = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+    if (s >= P.plane) return false;
+    j = s / P.nx;
+    i = s - j * P.nx;
+    return true;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_bhalf(Params P, int k0r, FieldsT<T> f, T h, T *murbuf) {
-    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= P.nc) return;
-    int i = (int)(o % P.nx);
-    int64_t r = o / P.nx;
-    int j = (int)(r % P.ny);
-    int p = (int)(r / P.ny);
+    int i, j;
+    if (!plane_cell(P, i, j)) return;
+    const int p = (int)blockIdx.y;
+    const int64_t o = (int64_t)p * P.plane + i + (int64_t)P.nx * j;
     int l = p - k0r;
     if (l < 0) l += P.nz;
     int64_t oi = o + ((i + 1 == P.nx) ? 1 - P.nx : 1);
@@ -53,12 +62,10 @@ __global__ void __launch_bounds__(256) k_bhalf(Params P, int k0r, FieldsT<T> f, 
 template <typename T, typename JT>
 __global__ void __launch_bounds__(256) k_eupdate(Params P, int k0r, FieldsT<T> f, JT *Jx, JT *Jy, JT *Jz,
                                                  const JT *jion, T dt) {
-    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= P.nc) return;
-    int i = (int)(o % P.nx);
-    int64_t r = o / P.nx;
-    int j = (int)(r % P.ny);
-    int p = (int)(r / P.ny);
+    int i, j;
+    if (!plane_cell(P, i, j)) return;
+    const int p = (int)blockIdx.y;
+    const int64_t o = (int64_t)p * P.plane + i + (int64_t)P.nx * j;
     int l = p - k0r;
     if (l < 0) l += P.nz;
     int64_t oi = o - ((i == 0) ? 1 - P.nx : 1);
@@ -113,13 +120,13 @@ __global__ void k_mur_shift(Params P, int k0r, int shift, int front_mur, FieldsT
 
 template <typename T>
 void launch_bhalf(const Params &P, int k0r, FieldsT<T> f, T h, T *murbuf, hipStream_t st) {
-    hipLaunchKernelGGL(k_bhalf<T>, dim3(nblocks(P.nc, 256)), dim3(256), 0, st, P, k0r, f, h, murbuf);
+    hipLaunchKernelGGL(k_bhalf<T>, dim3(nblocks(P.plane, 256), P.nz), dim3(256), 0, st, P, k0r, f, h, murbuf);
 }
 
 template <typename T, typename JT>
 void launch_eupdate(const Params &P, int k0r, FieldsT<T> f, JT *J[3], const JT *jion, T dt, hipStream_t st) {
-    hipLaunchKernelGGL((k_eupdate<T, JT>), dim3(nblocks(P.nc, 256)), dim3(256), 0, st, P, k0r, f, J[0], J[1], J[2],
-                       jion, dt);
+    hipLaunchKernelGGL((k_eupdate<T, JT>), dim3(nblocks(P.plane, 256), P.nz), dim3(256), 0, st, P, k0r, f, J[0], J[1],
+                       J[2], jion, dt);
 }
 
 template <typename T, typename JT>

@@ -49,6 +49,7 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (g->nx < 1 || g->ny < 1 || g->nz < 16) return fail(err, PIC_EINVAL, "grid: need nx, ny >= 1 and nz >= 16");
     if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 31)
         return fail(err, PIC_EINVAL, "grid: more than 2^31 cells");
+    if (g->nz > 65535) return fail(err, PIC_EINVAL, "grid: nz <= 65535 (one launch row per plane)");
     if (!(g->dx_m > 0) || !(g->cfl > 0 && g->cfl <= 1.0)) return fail(err, PIC_EINVAL, "grid: dx_m > 0, 0 < cfl <= 1");
     if (!(f->gamma_boost >= 1.0)) return fail(err, PIC_EINVAL, "frame: gamma_boost >= 1");
     if (f->window_beta >= 1.0) return fail(err, PIC_EINVAL, "frame: window_beta < 1");

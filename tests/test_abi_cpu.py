@@ -86,6 +86,7 @@ def test_layout_scales_with_capacity():
 
 @pytest.mark.parametrize("mutate,expect", [
     (lambda w: w["grid"].update(nz=8), abi.PIC_EINVAL),
+    (lambda w: w["grid"].update(nx=1, ny=1, nz=65536), abi.PIC_EINVAL),
     (lambda w: w["grid"].update(cfl=1.5), abi.PIC_EINVAL),
     (lambda w: w["frame"].update(gamma_boost=0.5), abi.PIC_EINVAL),
     (lambda w: w["undulator"].update(kind=1, period_lab_m=0.0), abi.PIC_EINVAL),
