@@ -496,7 +496,7 @@ pic_status adjoint_seed(Ctx &c, double kb, double *lam, double *loss) {
 // slots of plasma after the forward step's injection (host replay of the sheet logic)
 static int64_t plasma_slots_after(const Ctx &c, const StepCtx &S) {
     if (!c.P.has_plasma) return c.np_slots;
-    int64_t sheet = (int64_t)c.P.plane * c.P.ppx * c.P.ppy;
+    int64_t sheet = sheet_particles(c.P);
     double hi = (double)(S.k0n + c.P.nz - 4);
     int64_t l = c.sh_hi, n = c.np_slots;
     while (sheet_z(l, c.P.ppz, c.P.bR, S.t1) < hi) {
