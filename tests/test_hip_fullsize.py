@@ -26,9 +26,9 @@ W = pin.workload(1)
 FIELDS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
 
 
-def _gpu(precision=1, **kw):
+def _gpu(precision=1, w=W, **kw):
     from paper_2411_04703_amd.sim import Sim
-    return Sim(W, pin.beam_normals(W["beam"]["n_macro"], 0), precision=precision, **kw)
+    return Sim(w, pin.beam_normals(w["beam"]["n_macro"], 0), precision=precision, **kw)
 
 
 def _oracle_grid():
@@ -38,15 +38,15 @@ def _oracle_grid():
     return po.Sim(w, pin.beam_normals(16, 0))
 
 
-def _predict(ref, p, idx, dt, pusher):
-    """Oracle gather (at B^n), push and move of particles idx of state p."""
+def _predict(ref, p, idx, dt, pusher, qm=-1.0):
+    """Oracle gather (at B^n), push and move of particles idx of state p (charge-to-mass ratio qm)."""
     X = np.stack([p["x"][idx], p["y"][idx], p["z"][idx]], axis=1)
     U = np.stack([p["ux"][idx], p["uy"][idx], p["uz"][idx]], axis=1)
     X1 = np.empty_like(X)
     U1 = np.empty_like(U)
     for k in range(len(idx)):
         E, B = ref.gather(X[k])
-        u1 = po.push(pusher, -1.0, dt, U[k], E, B)
+        u1 = po.push(pusher, qm, dt, U[k], E, B)
         X1[k] = X[k] + dt * u1 / math.sqrt(1.0 + u1 @ u1)
         U1[k] = u1
     return X1, U1
@@ -95,6 +95,41 @@ def test_workload1_sampled_particles_follow_the_oracle_push():
         # FP32 offsets and FP32 fields: ~1e-6 cells; neighbours are >= 0.05 cells apart
         assert np.quantile(d, 0.999) < 2e-5 and d.max() < 1e-4, (sp, np.sort(d)[-5:])
         assert du.max() < 1e-5, (sp, np.sort(du)[-5:])
+
+
+def test_workload1_mobile_ions_follow_the_oracle_push():
+    """Mobile ions of mass 4 at full size: sampled ions near the beam are pushed
+    by the oracle (q/m = +1/4) from the GPU's fields and found among the GPU's
+    ions (negative weights) of the next state, to the bars of the electrons."""
+    from paper_2411_04703_amd import abi
+    w = pin.scaled(W)
+    w["plasma"].update(ions=2, ion_mass=4.0)
+    gpu = _gpu(w=w)
+    gpu.step(3)
+    ref = _oracle_grid()
+    for f in FIELDS:
+        ref.field(f)[:] = gpu.field(f)
+    ref.b_half()
+    i = ref.info()
+    k0 = int(gpu.diag()["k0"])
+    rng = np.random.default_rng(12)
+    before = gpu.particles(1)
+    gpu.step(1)
+    pa = gpu.particles(1)
+    after = {k: v[pa["w"] < 0] for k, v in pa.items()}
+    ion = before["w"] < 0
+    p = {k: v[ion] for k, v in before.items()}
+    p["z"] = p["z"] - k0
+    near = np.nonzero((np.abs(p["x"] - 64) < 6) & (np.abs(p["y"] - 64) < 6) &
+                      (np.abs(p["z"] - W["beam"]["z_center_cells"]) < 60))[0]
+    idx = rng.choice(near, 1500, replace=False)
+    X1, U1 = _predict(ref, p, idx, i.dt, abi.PIC_BORIS, qm=0.25)
+    X1[:, 2] += k0
+    d, du = _match(X1, U1, after)
+    assert np.quantile(d, 0.999) < 2e-5 and d.max() < 1e-4, np.sort(d)[-5:]
+    assert du.max() < 1e-5, np.sort(du)[-5:]
+    # the ions did respond to the beam's field (the push is not the identity)
+    assert np.abs(U1[:, :2]).max() > 1e-7
 
 
 def test_workload1_charge_conservation_and_counts():
