@@ -28,6 +28,8 @@ struct Params {
     int cbx, cby, lgx, lgy, lgz, pad3;
     // mobile ions: mass in electron masses, and the pusher's half-step factor 0.5 (q/m) dt = 0.5 dt / mi
     double mi, ahi;
+    float idt32;  // FP32 mode: 1 / dt rounded to FP32 (the deposit's w / dt is w * idt32)
+    int pad4;
 };
 
 // Window position during one step (host-decided, deterministic from the step count).
@@ -172,10 +174,10 @@ template <typename T> __device__ inline void cross3(const T a[3], const T b[3], 
 template <typename T> __device__ inline void push_boris(T a, const T u[3], const T E[3], const T B[3], T out[3]) {
     T um[3], Tv[3], S[3], up[3], c[3];
     for (int d = 0; d < 3; ++d) um[d] = u[d] + a * E[d];
-    T gm = sqrt(T(1) + dot3(um, um));
-    for (int d = 0; d < 3; ++d) Tv[d] = a * B[d] / gm;
-    T tt = dot3(Tv, Tv);
-    for (int d = 0; d < 3; ++d) S[d] = T(2) * Tv[d] / (T(1) + tt);
+    const T igm = T(1) / sqrt(T(1) + dot3(um, um));  // one division per push, then products
+    for (int d = 0; d < 3; ++d) Tv[d] = a * B[d] * igm;
+    const T sc = T(2) / (T(1) + dot3(Tv, Tv));
+    for (int d = 0; d < 3; ++d) S[d] = sc * Tv[d];
     cross3(um, Tv, c);
     for (int d = 0; d < 3; ++d) up[d] = um[d] + c[d];
     cross3(up, S, c);
@@ -184,17 +186,17 @@ template <typename T> __device__ inline void push_boris(T a, const T u[3], const
 
 // Vay: velocity average in the magnetic term, closed-form Lorentz factor.
 template <typename T> __device__ inline void push_vay(T a, const T u[3], const T E[3], const T B[3], T out[3]) {
-    T g0 = sqrt(T(1) + dot3(u, u));
+    const T ig0 = T(1) / sqrt(T(1) + dot3(u, u));
     T v0[3], c[3], u1[3], tau[3], t[3];
-    for (int d = 0; d < 3; ++d) v0[d] = u[d] / g0;
+    for (int d = 0; d < 3; ++d) v0[d] = u[d] * ig0;
     cross3(v0, B, c);
     for (int d = 0; d < 3; ++d) u1[d] = u[d] + T(2) * a * E[d] + a * c[d];
     for (int d = 0; d < 3; ++d) tau[d] = a * B[d];
     T us = dot3(u1, tau), tau2 = dot3(tau, tau);
     T sig = T(1) + dot3(u1, u1) - tau2;
     T D = sqrt(sig * sig + T(4) * (tau2 + us * us));
-    T gn = sqrt(T(0.5) * (sig + D));
-    for (int d = 0; d < 3; ++d) t[d] = tau[d] / gn;
+    const T ign = T(1) / sqrt(T(0.5) * (sig + D));
+    for (int d = 0; d < 3; ++d) t[d] = tau[d] * ign;
     T sf = T(1) / (T(1) + dot3(t, t));
     T ut = dot3(u1, t);
     cross3(u1, t, c);

@@ -573,7 +573,8 @@ __device__ inline bool advance(const Params &P, float EB[6], bool ext, double a_
     float E[3] = {EB[0], EB[1], EB[2]}, B[3] = {EB[3], EB[4], EB[5]};
     if (ext) ext32(P, a_l, cphi, sphi, q.o[2], E, B);
     if (!push32(P, q.w < 0.0f, E, B, q.u)) return false;
-    float ig = 1.0f / sqrtf(1.0f + q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
+    // 1 / gamma with the hardware reciprocal square root (1 ulp)
+    const float ig = __builtin_amdgcn_rsqf(1.0f + q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
     const float dt = (float)P.dt;
     for (int d = 0; d < 3; ++d) X1[d] = q.o[d] + dt * (q.u[d] * ig);
     return true;
@@ -601,7 +602,7 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
     Esk e;
     esk_setup(q.o, X1, e);
     long long *J[3] = {Jx, Jy, Jz};
-    const float fq = q.w / (float)P.dt;
+    const float fq = q.w * P.idt32;
     if (!fixed_ok(fq, P.fscale)) {
         atomicOr(flags, DFLAG_FIXED_OVERFLOW);
         return false;
@@ -760,7 +761,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                         atomicOr(flags, DFLAG_NONFINITE);
                         act = false;
                     } else {
-                        fq = q.w / (float)P.dt;
+                        fq = q.w * P.idt32;
                         if (!fixed_ok(fq, P.fscale)) {
                             atomicOr(flags, DFLAG_FIXED_OVERFLOW);
                             fq = 0.0f;
