@@ -317,3 +317,33 @@ def test_vacuum_ballistic_expansion_matches_lab_closed_form():
         pred = math.sqrt((dx @ dx + 2 * (dx @ du) * sdist + (du @ du) * sdist ** 2) / dx.size)
         assert abs(d1["sigma"][k] - pred) < 1e-3 * pred, (k, d1["sigma"][k], pred)
     assert d1["sigma"][0] > 1.05 * math.sqrt((x0["x"].var()))  # the beam did expand
+
+
+def _cold_plasma_energy_growth(gR, steps=(100, 300)):
+    """Field energy of a periodic 16 x 1 x 128 (x-z) box of cold plasma drifting
+    at -beta_R, seeded with 1e-6 transverse momentum noise: (E(steps[1]) / E(steps[0]))."""
+    w = pin.scaled(pin.workload(5), nx=16, ny=1, nz=128, n_beam=0)
+    w["frame"]["gamma_boost"] = gR
+    w["undulator"]["kind"] = 0
+    w["plasma"].update(n0_lab_cm3=1e16, ppc=[2, 1, 2], ions=1, length_lab_m=0.0)
+    s = po.Sim(w, pin.beam_normals(0), bc_z=1)
+    p = s.particles(1, view=True)
+    p["ux"][:] += 1e-6 * np.random.default_rng(0).standard_normal(len(p["ux"]))
+    energy = {}
+    for n in range(steps[1] + 1):
+        if n in steps:
+            energy[n] = sum(float((s.field(f) ** 2).sum()) for f in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"))
+        s.step(1)
+    return energy[steps[1]] / energy[steps[0]]
+
+
+def test_drifting_cold_plasma_shows_the_numerical_cherenkov_growth():
+    """The discretisation itself (Yee fields, quadratic shapes, no filter) lets a
+    cold plasma drifting at gamma_R = 20 grow a field mode from noise (the
+    numerical Cherenkov instability the paper's introduction discusses):
+    x7000 in 200 steps here, against x40 for the same plasma at rest (the
+    slower finite-grid growth of a cold plasma whose Debye length is far below
+    the cell).  This is the growth the long FP32 runs meet; the oracle shares
+    no code with them."""
+    drift, rest = _cold_plasma_energy_growth(20.0), _cold_plasma_energy_growth(1.0001)
+    assert drift > 1e3 and drift > 30 * rest, (drift, rest)
