@@ -319,14 +319,16 @@ def test_vacuum_ballistic_expansion_matches_lab_closed_form():
     assert d1["sigma"][0] > 1.05 * math.sqrt((x0["x"].var()))  # the beam did expand
 
 
-def _cold_plasma_energy_growth(gR, steps=(100, 300)):
-    """Field energy of a periodic 16 x 1 x 128 (x-z) box of cold plasma drifting
-    at -beta_R, seeded with 1e-6 transverse momentum noise: (E(steps[1]) / E(steps[0]))."""
+def _cold_plasma_energy_growth(gR, dt, t_span=(55.0, 165.0)):
+    """Growth rate per unit time of the field energy of a periodic 16 x 1 x 128
+    (x-z) box of cold plasma drifting at -beta_R, seeded with 1e-6 transverse
+    momentum noise, between the times t_span."""
+    steps = tuple(int(round(t / dt)) for t in t_span)
     w = pin.scaled(pin.workload(5), nx=16, ny=1, nz=128, n_beam=0)
     w["frame"]["gamma_boost"] = gR
     w["undulator"]["kind"] = 0
     w["plasma"].update(n0_lab_cm3=1e16, ppc=[2, 1, 2], ions=1, length_lab_m=0.0)
-    s = po.Sim(w, pin.beam_normals(0), bc_z=1)
+    s = po.Sim(w, pin.beam_normals(0), bc_z=1, dt_override=dt)
     p = s.particles(1, view=True)
     p["ux"][:] += 1e-6 * np.random.default_rng(0).standard_normal(len(p["ux"]))
     energy = {}
@@ -334,16 +336,20 @@ def _cold_plasma_energy_growth(gR, steps=(100, 300)):
         if n in steps:
             energy[n] = sum(float((s.field(f) ** 2).sum()) for f in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"))
         s.step(1)
-    return energy[steps[1]] / energy[steps[0]]
+    return math.log(energy[steps[1]] / energy[steps[0]]) / (steps[1] - steps[0]) / dt
 
 
-def test_drifting_cold_plasma_shows_the_numerical_cherenkov_growth():
+def test_drifting_cold_plasma_growth_and_the_half_cell_time_step():
     """The discretisation itself (Yee fields, quadratic shapes, no filter) lets a
     cold plasma drifting at gamma_R = 20 grow a field mode from noise (the
-    numerical Cherenkov instability the paper's introduction discusses):
-    x7000 in 200 steps here, against x40 for the same plasma at rest (the
-    slower finite-grid growth of a cold plasma whose Debye length is far below
-    the cell).  This is the growth the long FP32 runs meet; the oracle shares
-    no code with them."""
-    drift, rest = _cold_plasma_energy_growth(20.0), _cold_plasma_energy_growth(1.0001)
-    assert drift > 1e3 and drift > 30 * rest, (drift, rest)
+    numerical Cherenkov instability the paper's introduction discusses): at
+    c dt = 0.95 dx / sqrt(3) its energy grows at 0.08 per unit time, against
+    0.03 for the same plasma at rest (the slower finite-grid growth of a cold
+    plasma whose Debye length is far below the cell).  At c dt = dx / 2, the
+    step the workloads use, the drifting plasma grows at 0.02: the drift adds
+    nothing."""
+    fast = _cold_plasma_energy_growth(20.0, 0.95 / math.sqrt(3.0))
+    half = _cold_plasma_energy_growth(20.0, 0.5)
+    rest = _cold_plasma_energy_growth(1.0001, 0.5)
+    assert fast > 2.5 * half, (fast, half)
+    assert half < 1.5 * rest, (half, rest)
