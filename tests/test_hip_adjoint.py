@@ -44,7 +44,7 @@ def test_adjoint_subcase_matches_central_differences(K, n0):
     w["beam"]["charge_C"] = 3e-9
     nrm = pin.beam_normals(w["beam"]["n_macro"], 7)
     w["frame"]["window_beta"] = po.Sim(w, nrm).info().bw
-    _check(w, nrm, 40, 10)
+    _check(w, nrm, 48, 12)
 
 
 def test_adjoint_workload3_matches_central_differences():
@@ -118,10 +118,10 @@ def test_fp32_mode_adjoint_matches_fp64_mode_and_differences(K, n0):
     w["beam"]["charge_C"] = 3e-9
     nrm = pin.beam_normals(w["beam"]["n_macro"], 7)
     w["frame"]["window_beta"] = po.Sim(w, nrm).info().bw
-    L64, gK64, gn64 = bunching_grad(w, nrm, 40, every=10)
-    L32, gK32, gn32 = bunching_grad(w, nrm, 40, every=10, precision=abi.PIC_FP32_SPLIT)
+    L64, gK64, gn64 = bunching_grad(w, nrm, 48, every=12)
+    L32, gK32, gn32 = bunching_grad(w, nrm, 48, every=12, precision=abi.PIC_FP32_SPLIT)
     assert L32 == pytest.approx(L64, rel=1e-4)
     assert gK32 == pytest.approx(gK64, rel=1e-3), (gK32, gK64)
     assert gn32 == pytest.approx(gn64, rel=1e-3), (gn32, gn64)
-    fK = (_loss(w, nrm, 40, 10, K * (1 + H), n0) - _loss(w, nrm, 40, 10, K * (1 - H), n0)) / (2 * H)
+    fK = (_loss(w, nrm, 48, 12, K * (1 + H), n0) - _loss(w, nrm, 48, 12, K * (1 - H), n0)) / (2 * H)
     assert gK32 == pytest.approx(fK, rel=1e-3)
