@@ -284,7 +284,7 @@ def main():
         "dtype": "f32" if prec == abi.PIC_FP32_SPLIT else "f64",
         "data": "synthetic",
         "config": {"workload": "128x128x512 cells, gamma_R=20, beam 4,194,304 macroparticles (sigma 4x4x32 cells, "
-                               "lab gamma 200) + cold plasma 1e16 cm^-3 at 2 ppc with immobile ions",
+                               "lab gamma 200) + cold plasma 1e16 cm^-3 at 2 ppc with immobile ions, c dt = dx/2",
                    "particles_active": n_active, "cells": n_cells,
                    "precision": "fp32_split_fixed_point" if prec == abi.PIC_FP32_SPLIT else "fp64_plain",
                    "deposit_variant": args.variant, "tile": tile_used, "wg_per_cu": args.wg_per_cu},
