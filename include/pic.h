@@ -61,7 +61,9 @@ enum { PIC_BORIS = 0, PIC_VAY = 1, PIC_PUSHER_AUTO = -1 };
 enum { PIC_UND_NONE = 0, PIC_UND_HELICAL = 1, PIC_UND_PLANAR = 2 };
 
 /* Boosted-frame grid: nx x ny x nz cubic cells of edge dx_m; x, y periodic,
- * z open (first-order Mur faces) with a moving window.  dt = cfl dx / (c sqrt 3). */
+ * z open (first-order Mur faces) with a moving window.  dt = cfl dx / (c sqrt 3),
+ * 0 < cfl <= 1, nz <= 65535.  cfl = sqrt(3)/2 (c dt = dx / 2) is where the Yee
+ * grid's numerical Cherenkov growth of a plasma drifting along z is slowest. */
 typedef struct {
     int32_t nx, ny, nz, reserved;
     double dx_m, cfl;
