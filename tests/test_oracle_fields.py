@@ -106,3 +106,66 @@ def test_moving_window_with_plasma_is_stable():
         s.step(20)
         e.append(s.diag(1.0)["field_energy"])
     assert max(e) < 1e-19, e
+
+
+def test_field_energy_of_three_modes_closed_form():
+    """The diagnostics' field energy 1/2 sum(E^2 + B^2) of three superposed
+    Fourier modes of different polarisation.  A mode with E^0 = A cos(k.x) and
+    B^(-1/2) = 0 has, by the Yee recurrence, E^n = A cos((n + 1/2) theta) /
+    cos(theta/2) and a B^(n-1/2) field of amplitude A sin(n theta) /
+    cos(theta/2) in units where its grid sum of squares is nc/2 like E's, so
+    field_energy(n) = sum_modes nc A^2 (cos^2((n + 1/2) theta) + sin^2(n theta))
+    / (4 cos^2(theta/2)); the modes are orthogonal, so no cross terms.  A
+    missing factor 1/2, a missing component or a B at the wrong time level
+    fails."""
+    nx, ny, nz = 16, 8, 12
+    s = _empty(nx, ny, nz, bc_z=1)
+    dt = s.info().dt
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    modes = [("Ez", (2, 1, 0), 1.3), ("Ey", (1, 0, 2), 0.7), ("Ex", (0, 2, 1), 2.1)]
+    thetas = []
+    for comp, ka, amp in modes:
+        k = (2 * math.pi * ka[0] / nx, 2 * math.pi * ka[1] / ny, 2 * math.pi * ka[2] / nz)
+        s.field(comp)[:] = amp * np.cos(k[0] * ii + k[1] * jj + k[2] * kk)
+        thetas.append(_theta(dt, k))
+    nc = nx * ny * nz
+
+    def expect(n):
+        return sum(nc * amp**2 * (math.cos((n + 0.5) * th) ** 2 + math.sin(n * th) ** 2) / (4 * math.cos(th / 2) ** 2)
+                   for (_, _, amp), th in zip(modes, thetas))
+
+    done = 0
+    for n in (0, 1, 5, 17, 40):
+        s.step(n - done)
+        done = n
+        fe = s.diag(1.0)["field_energy"]
+        assert fe == pytest.approx(expect(n), rel=1e-12), n
+    # B carries a sizeable share of the energy at n = 40
+    assert any(abs(math.sin(40 * th)) > 0.3 for th in thetas)
+
+
+def test_yee_discrete_energy_invariant():
+    """In a periodic vacuum box the Yee update keeps W^n = |E^n|^2 +
+    B^(n-1/2) . B^(n+1/2) exactly (the scheme's discrete energy), whatever the
+    initial fields; held to round-off over 60 steps from random fields."""
+    nx, ny, nz = 8, 6, 10
+    s = _empty(nx, ny, nz, bc_z=1)
+    rng = np.random.default_rng(11)
+    for c in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        s.field(c)[:] = rng.standard_normal((nz, ny, nx))
+
+    def fields():
+        return [s.field(c).copy() for c in ("Ex", "Ey", "Ez")], [s.field(c).copy() for c in ("Bx", "By", "Bz")]
+
+    E, B = fields()
+    ex0 = E[0].copy()
+    W = []
+    for _ in range(60):
+        s.step(1)
+        E1, B1 = fields()
+        W.append(sum((e * e).sum() for e in E) + sum((b0 * b1).sum() for b0, b1 in zip(B, B1)))
+        E, B = E1, B1
+    W = np.array(W)
+    assert np.abs(W - W[0]).max() <= 1e-12 * abs(W[0])
+    # the fields did evolve: the invariant is not met trivially
+    assert np.abs(E[0] - ex0).max() > 0.1 * np.abs(ex0).max()

@@ -9,7 +9,10 @@ problem of the boosted frame, section 1 field transformation).
   q / (4 pi gamma^2 r^2) along it (gamma^3 between the two);
 * quasi-statics: one Yee step of the oracle from this field moves the pattern
   with the beam, so E after one step equals the initial field of the moved
-  beam (a wrong sign or time level of B would launch a transient instead).
+  beam (a wrong sign or time level of B would launch a transient instead);
+* time level: B at t' = -dt/2 makes one leap-frog step from the initial field
+  third-order accurate in dt (residual / 8 per halving), where B at t' = 0 or
+  +dt/2 gives second order (residual / 4).
 """
 import math
 
@@ -125,3 +128,45 @@ def test_initial_field_moves_with_the_beam():
         scale = np.abs(eb).max()
         assert scale > 0
         assert np.abs(ea - eb).max() <= tol * scale, (f, np.abs(ea - eb).max() / scale)
+
+
+def _set_beam_fields(sim, shift_dt):
+    """The beam's self-field with B taken at t' = -shift_dt / 2 (shift_dt = dt: the library's reading)."""
+    beta = po.beam_mean_beta(sim)
+    gamma = 1.0 / math.sqrt((1.0 - beta) * (1.0 + beta))
+    _, E, B = po.relativistic_poisson(np.real(sim.rho(1)), gamma, beta, shift_dt)
+    for name, v in zip(po.FIELD_NAMES, E + B):
+        sim.field(name)[:] = v
+
+
+def _one_step_residual(w, nrm, dt, shift):
+    """max |E after one step of dt - E after 32 steps of dt/32| / max |E|, both started from the
+    beam's self-field with B at t' = -shift * (own step) / 2."""
+    coarse = po.Sim(w, nrm, dt_override=dt)
+    _set_beam_fields(coarse, shift * dt)
+    coarse.step(1)
+    fine = po.Sim(w, nrm, dt_override=dt / 32)
+    _set_beam_fields(fine, shift * dt / 32)
+    fine.step(32)
+    num = max(np.abs(coarse.field(n) - fine.field(n)).max() for n in ("Ex", "Ey", "Ez"))
+    return num / max(np.abs(fine.field(n)).max() for n in ("Ex", "Ey", "Ez"))
+
+
+def test_initial_b_time_level_converges_at_third_order():
+    """The state between steps is (E^n, B^(n-1/2)), so the initial B must be
+    the moving pattern's B half a step earlier.  Taken so, B^(-1/2) is off by
+    O(dt^2) and one leap-frog step from it is off by O(dt^3) from the same
+    start resolved with 32 small steps: halving dt divides the residual by 8.
+    B taken at t' = 0, or half a step late, is off by O(dt) and the residual
+    falls only as dt^2 (ratio 4), and is 50x larger at the smaller step."""
+    w = _beam_only(nx=16, ny=16, nz=48, n=16384, sigma=(3, 3, 6))
+    w["beam"]["charge_C"] = 3e-12  # the orbits stay straight over the step
+    w["beam"]["rel_energy_spread_rms"] = 0.0
+    w["beam"]["emit_n_m"] = [1e-12, 1e-12]
+    w["frame"]["window_beta"] = 0.0
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 2)
+    res = {shift: [_one_step_residual(w, nrm, dt, shift) for dt in (0.1, 0.05)] for shift in (1, 0, -1)}
+    assert 7.0 < res[1][0] / res[1][1] < 9.0, res
+    for wrong in (0, -1):
+        assert 3.9 < res[wrong][0] / res[wrong][1] < 4.1, res
+        assert res[wrong][1] > 30 * res[1][1], res
