@@ -217,6 +217,7 @@ typedef struct {
     double field_energy, kin_beam, kin_plasma;
     double gauss_max, gauss_drift, rho_max;
     double window_beta, frac_bits, error_flags;
+    double window_x; /* window position (cells) at t; k0 is its floor, or lags it by the one shift a step allows */
 } pic_diag_out;
 PIC_API pic_status pic_diag(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_diag_out *out);
 
@@ -294,6 +295,19 @@ PIC_API pic_status pic_adjoint_step(pic_ctx *c, void *lam, double grad[2]);
  * returns the summed milliseconds and the number of timed launches per class. */
 PIC_API pic_status pic_timing(pic_ctx *c, int32_t enable);
 PIC_API pic_status pic_timing_read(pic_ctx *c, double ms[4], int64_t launches[4]);
+
+/* Window speed (section 3: a beam whose mean velocity changes, e.g. on entering
+ * an undulator, drifts through a window at a fixed speed; the window's speed is
+ * adjusted to keep it).  From the current step on the window moves at beta
+ * (units of c): its position is x0 + beta (t' - t0), x0 its position at the
+ * call's time t0, and it shifts one cell whenever that position passes the next
+ * whole cell (at most one shift per step).  beta in [0, 1]; a moving window
+ * must keep moving (beta > 0) and a window at rest stays at rest (PIC_EINVAL
+ * otherwise).  Host only, no synchronisation; the setting is part of the
+ * checkpointed state.  The adjoint's recomputation replays checkpoints, so a
+ * run whose window speed was changed between checkpoints is not
+ * differentiated. */
+PIC_API pic_status pic_set_window_beta(pic_ctx *c, double beta);
 
 PIC_API pic_status pic_sync(pic_ctx *c);
 PIC_API void pic_free(pic_ctx *c);

@@ -51,6 +51,13 @@ struct orc_sim {
     int nx, ny, nz, periodic_z;
     int64_t nc;
     double dt, gR, bR, uR, bw, nref, zoff;
+    double win_x0, win_t0; /* window position at time t: win_x0 + bw (t - win_t0) (cells) */
+    /* neutralising charge of the beam at t' = 0, faded linearly over fc_T (section 3):
+     * charge -fc_rho f(t), f = max(0, 1 - t / fc_T), carried off by the current -fc_E f'(t),
+     * fc_E the field of the beam's charge (div fc_E = fc_rho); absolute planes from fc_k0 */
+    real *fc_rho, *fc_E[3];
+    double fc_T;
+    int64_t fc_k0;
     double ku, z0u, Lu, Ru;      /* undulator (lab cells) */
     double z0p, Lp, Rp;          /* plasma (lab cells) */
     double F, sig_zlab;
@@ -633,6 +640,8 @@ void orc_free(orc_sim *s) {
         free(s->J[q]);
     }
     for (int sp = 0; sp < 3; ++sp) sp_free(&s->sp[sp]);
+    free(s->fc_rho);
+    for (int c = 0; c < 3; ++c) free(s->fc_E[c]);
     free(s);
 }
 
@@ -691,7 +700,7 @@ static void shift_fields(orc_sim *s) {
  * front.  Returns whether the window shifted. */
 static int window_events(orc_sim *s, double t1) {
     int shifted = 0;
-    int64_t target = (int64_t)floor(s->bw * t1);
+    int64_t target = (int64_t)floor(s->win_x0 + s->bw * (t1 - s->win_t0));
     while (s->k0 < target) {
         shift_fields(s);
         shifted = 1;
@@ -719,6 +728,40 @@ static int window_events(orc_sim *s, double t1) {
     return shifted;
 }
 
+/* remaining fraction of the neutralising charge at time t */
+static double fade_of(const orc_sim *s, double t) {
+    if (!(s->fc_T > 0.0)) return 0.0;
+    double f = 1.0 - t / s->fc_T;
+    return f > 0.0 ? f : 0.0;
+}
+
+/* the current that removes the neutralising charge between t and t1: the charge drops by
+ * fc_rho (f(t) - f(t1)), so -fc_E (f(t) - f(t1)) / dt satisfies continuity node by node */
+static void fading_charge_current(orc_sim *s, double t, double t1) {
+    double a = (fade_of(s, t) - fade_of(s, t1)) / s->dt;
+    if (a == 0.0) return;
+    int64_t pl = (int64_t)s->nx * s->ny;
+    for (int l = 0; l < s->nz; ++l) {
+        int64_t k = s->k0 + l - s->fc_k0; /* the plane where the charge was laid down */
+        if (k < 0 || k >= s->nz) continue;
+        for (int c = 0; c < 3; ++c)
+            for (int64_t q = 0; q < pl; ++q) s->J[c][l * pl + q] -= a * s->fc_E[c][k * pl + q];
+    }
+}
+
+void orc_set_fading_charge(orc_sim *s, const real *rho, const real *Ex, const real *Ey, const real *Ez,
+                           double fade_s) {
+    const real *E[3] = {Ex, Ey, Ez};
+    if (!s->fc_rho) {
+        s->fc_rho = (real *)malloc(sizeof(real) * s->nc);
+        for (int c = 0; c < 3; ++c) s->fc_E[c] = (real *)malloc(sizeof(real) * s->nc);
+    }
+    memcpy(s->fc_rho, rho, sizeof(real) * s->nc);
+    for (int c = 0; c < 3; ++c) memcpy(s->fc_E[c], E[c], sizeof(real) * s->nc);
+    s->fc_T = fade_s * C_LIGHT / s->c.dx_m;
+    s->fc_k0 = s->k0;
+}
+
 static void step_once(orc_sim *s) {
     double t = s->step * s->dt, t1 = (s->step + 1) * s->dt;
     orc_b_half(s); /* B^n */
@@ -729,6 +772,7 @@ static void step_once(orc_sim *s) {
             if (p->alive[q]) particle_update(s, sp, q, t);
     }
     orc_ion_current(s, t, t1, 0);
+    fading_charge_current(s, t, t1);
     orc_b_half(s); /* B^{n+1/2} */
     orc_e_update(s);
     s->step += 1;
@@ -737,6 +781,15 @@ static void step_once(orc_sim *s) {
 
 void orc_step(orc_sim *s, int32_t n) {
     for (int32_t i = 0; i < n; ++i) step_once(s);
+}
+
+/* the window moves at beta from the current time on (section 3: the window's speed is
+ * adjusted to the beam's); its position stays continuous in time */
+void orc_set_window_beta(orc_sim *s, double beta) {
+    double t = s->step * s->dt;
+    s->win_x0 = s->win_x0 + s->bw * (t - s->win_t0);
+    s->win_t0 = t;
+    s->bw = beta;
 }
 
 /* ------------------------------------------------------------------ */
@@ -766,6 +819,7 @@ void orc_info(const orc_sim *s, orc_info_t *o) {
     o->plasma_removed = s->plasma_removed;
     o->n_ions = s->sp[2].n;
     o->ion_mass = s->m[2];
+    o->window_x = s->win_x0 + s->bw * (s->step * s->dt - s->win_t0);
 }
 
 real *orc_field(orc_sim *s, int32_t which) {
@@ -805,6 +859,15 @@ void orc_rho(orc_sim *s, int32_t mask, real *rho) {
                     }
         }
     }
+    if ((mask & 8) && s->fc_rho) {
+        double f = fade_of(s, s->step * s->dt);
+        int64_t pl = (int64_t)s->nx * s->ny;
+        for (int l = 0; l < s->nz; ++l) {
+            int64_t k = s->k0 + l - s->fc_k0;
+            if (f == 0.0 || k < 0 || k >= s->nz) continue;
+            for (int64_t q = 0; q < pl; ++q) rho[l * pl + q] -= f * s->fc_rho[k * pl + q];
+        }
+    }
     if ((mask & 4) && s->c.ions == 1) {
         double t = s->step * s->dt;
         int ptr = s->c.ppc[0] * s->c.ppc[1];
@@ -824,7 +887,7 @@ void orc_rho(orc_sim *s, int32_t mask, real *rho) {
 
 /* r = div E - rho on every node (div of the edge-centred E at the node) */
 void orc_gauss(orc_sim *s, real *r) {
-    orc_rho(s, 7, r);
+    orc_rho(s, 15, r);
     for (int l = 0; l < s->nz; ++l)
         for (int j = 0; j < s->ny; ++j)
             for (int i = 0; i < s->nx; ++i) {

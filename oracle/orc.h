@@ -57,6 +57,7 @@ typedef struct {
     int64_t k0, step, n_beam, n_plasma, sheet_lo, sheet_hi, beam_lost, plasma_removed;
     int64_t n_ions; /* mobile ion slots (n_plasma counts electron slots) */
     double ion_mass;
+    double window_x; /* window position (cells) at the current time */
 } orc_info_t;
 
 typedef struct {
@@ -72,6 +73,7 @@ typedef struct orc_sim orc_sim;
 orc_sim *orc_new(const orc_config *c, const double *normals);
 void orc_free(orc_sim *s);
 void orc_step(orc_sim *s, int32_t n);
+void orc_set_window_beta(orc_sim *s, double beta); /* window speed from now on */
 void orc_info(const orc_sim *s, orc_info_t *out);
 void orc_diag(orc_sim *s, double kb, orc_diag_t *out);
 
@@ -91,7 +93,11 @@ void orc_deposit(orc_sim *s, const real X0[3], const real X1[3], real qw); /* ad
 void orc_ion_current(orc_sim *s, double t0, double t1, int32_t unit_weight); /* adds ion J_z into J */
 void orc_b_half(orc_sim *s);
 void orc_e_update(orc_sim *s);
-void orc_rho(orc_sim *s, int32_t mask, real *rho);   /* mask: 1 beam, 2 plasma electrons, 4 ions */
+void orc_rho(orc_sim *s, int32_t mask, real *rho);   /* mask: 1 beam, 2 plasma electrons, 4 ions, 8 neutraliser */
+/* neutralising charge -rho (node charge of the window at its current origin) faded linearly over
+ * fade_s seconds (boosted frame), removed by the current -E d/dt(fade), E its field (div E = rho) */
+void orc_set_fading_charge(orc_sim *s, const real *rho, const real *Ex, const real *Ey, const real *Ez,
+                           double fade_s);
 void orc_gauss(orc_sim *s, real *r);                 /* r = div E - rho on every node */
 void orc_zero_J(orc_sim *s);
 

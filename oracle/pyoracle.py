@@ -37,7 +37,7 @@ class Info(C.Structure):
                 ("dt", "gR", "bR", "uR", "bw", "nref_m3", "wbeam", "ku", "B0", "n0n", "zoff", "F_elong", "sig_zlab")] + \
                [(n, C.c_int64) for n in
                 ("k0", "step", "n_beam", "n_plasma", "sheet_lo", "sheet_hi", "beam_lost", "plasma_removed",
-                 "n_ions")] + [("ion_mass", C.c_double)]
+                 "n_ions")] + [("ion_mass", C.c_double), ("window_x", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -72,6 +72,8 @@ def lib(complex_step: bool = False):
         L.orc_new.argtypes = [C.POINTER(Config), C.c_void_p]
         L.orc_free.argtypes = [R]
         L.orc_step.argtypes = [R, C.c_int32]
+        L.orc_set_window_beta.argtypes = [R, C.c_double]
+        L.orc_set_fading_charge.argtypes = [R, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]
         L.orc_info.argtypes = [R, C.POINTER(Info)]
         L.orc_diag.argtypes = [R, C.c_double, C.POINTER(Diag)]
         L.orc_field.restype = C.c_void_p
@@ -169,6 +171,10 @@ class Sim:
 
     def step(self, n: int = 1):
         self.L.orc_step(self.h, int(n))
+
+    def set_window_beta(self, beta: float):
+        """The window moves at beta (units of c) from the current step on."""
+        self.L.orc_set_window_beta(self.h, float(beta))
 
     def info(self) -> Info:
         i = Info()
@@ -343,6 +349,17 @@ def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: flo
     By = beta_b * ((1.0 - w) * Ex + w * Exu)
     Bz = np.zeros_like(phi)
     return phi, (Ex, Ey, Ez), (Bx, By, Bz)
+
+
+def init_neutraliser(sim: "Sim", fade_s: float):
+    """Section 3's neutralising ions: a charge equal and opposite to the beam's at t' = 0, faded
+    linearly to zero over fade_s seconds (boosted frame) while the fields start from zero; its
+    field is the beam charge's electrostatic field (the relativistic Poisson problem at rest)."""
+    rho = np.real(sim.rho(1))
+    _, E, _ = relativistic_poisson(rho, 1.0, 0.0, sim.info().dt)
+    arrs = [np.ascontiguousarray(a, dtype=sim.dtype) for a in (rho,) + tuple(E)]
+    sim.L.orc_set_fading_charge(sim.h, *[a.ctypes.data for a in arrs], float(fade_s))
+    return arrs
 
 
 def beam_mean_beta(sim: "Sim") -> float:

@@ -73,7 +73,7 @@ class pic_diag_out(C.Structure):
                 ("usigma", C.c_double * 3), ("emit", C.c_double * 2)] + \
                [(n, C.c_double) for n in ("b1_re", "b1_im", "b1_abs", "b2_re", "b2_im", "b2_abs", "field_energy",
                                           "kin_beam", "kin_plasma", "gauss_max", "gauss_drift", "rho_max",
-                                          "window_beta", "frac_bits", "error_flags")]
+                                          "window_beta", "frac_bits", "error_flags", "window_x")]
 
     def as_dict(self):
         out = {}
@@ -86,7 +86,7 @@ class pic_diag_out(C.Structure):
 EXPORTS = ("pic_query_layout", "pic_derive", "pic_init", "pic_step", "pic_diag", "pic_read", "pic_write",
            "pic_get_state", "pic_set_state", "pic_lambda_len", "pic_adjoint_seed_bunching", "pic_adjoint_step",
            "pic_timing", "pic_timing_read", "pic_sync", "pic_free", "pic_last_error", "pic_state_to_fp64",
-           "pic_lab_probe", "pic_lab_probe_read")
+           "pic_lab_probe", "pic_lab_probe_read", "pic_set_window_beta")
 
 _lib = None
 
@@ -120,6 +120,7 @@ def load() -> C.CDLL:
     L.pic_lab_probe_read.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
     L.pic_timing.argtypes = [C.c_void_p, C.c_int32]
     L.pic_timing_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
+    L.pic_set_window_beta.argtypes = [C.c_void_p, C.c_double]
     L.pic_sync.argtypes = [C.c_void_p]
     L.pic_free.argtypes = [C.c_void_p]
     L.pic_last_error.argtypes = [C.c_void_p]

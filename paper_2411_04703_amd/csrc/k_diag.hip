@@ -269,6 +269,7 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
     o->step = (double)c.step;
     o->k0 = (double)c.k0;
     o->window_beta = c.bw;
+    o->window_x = c.win_x0 + c.bw * ((double)c.step * P.dt - c.win_t0);
     o->frac_bits = P.frac_bits;
     int k0r = (int)(c.k0 % P.nz);
     // beam as FP64 arrays

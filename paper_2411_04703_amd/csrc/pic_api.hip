@@ -309,7 +309,7 @@ StepCtx make_step_ctx(const Ctx &c) {
     S.t = (double)c.step * c.P.dt;
     S.t1 = (double)(c.step + 1) * c.P.dt;
     S.k0 = c.k0;
-    int64_t target = (int64_t)floor(c.bw * S.t1);
+    int64_t target = (int64_t)floor(c.win_x0 + c.bw * (S.t1 - c.win_t0));
     S.shift = c.k0 < target ? 1 : 0;
     S.k0n = c.k0 + S.shift;
     S.k0r = (int)(S.k0 % c.P.nz);
@@ -695,6 +695,23 @@ pic_status pic_timing_read(pic_ctx *c, double ms[4], int64_t launches[4]) {
     return PIC_OK;
 }
 
+pic_status pic_set_window_beta(pic_ctx *c, double beta) {
+    if (!c) return PIC_EINVAL;
+    if (!(beta >= 0.0 && beta <= 1.0)) {
+        c->err = "pic_set_window_beta: beta must lie in [0, 1]";
+        return PIC_EINVAL;
+    }
+    if ((c->bw > 0.0) != (beta > 0.0)) {
+        c->err = "pic_set_window_beta: a moving window cannot stop, nor a window at rest start moving";
+        return PIC_EINVAL;
+    }
+    const double t = (double)c->step * c->P.dt;
+    c->win_x0 = c->win_x0 + c->bw * (t - c->win_t0);
+    c->win_t0 = t;
+    c->bw = beta;
+    return PIC_OK;
+}
+
 pic_status pic_sync(pic_ctx *c) {
     if (!c) return PIC_EINVAL;
     PIC_HIP(*c, hipStreamSynchronize(c->st));
@@ -822,14 +839,14 @@ struct StateHeader {
     uint64_t magic, bytes;
     int64_t step, k0, sh_lo, sh_hi, nb_slots, np_slots;
     int32_t cur32, precision;
-    double bw;
+    double bw, win_x0, win_t0;
 };
 
 pic_status pic_get_state(pic_ctx *c, void *dst) {
     if (!c || !dst) return PIC_EINVAL;
     char *d = (char *)dst;
     StateHeader h = {0x5049435354415445ull, c->state_bytes, c->step, c->k0, c->sh_lo, c->sh_hi,
-                     c->nb_slots, c->np_slots, c->cur32, c->precision, c->bw};
+                     c->nb_slots, c->np_slots, c->cur32, c->precision, c->bw, c->win_x0, c->win_t0};
     PIC_HIP(*c, hipMemcpyAsync(d, &h, sizeof h, hipMemcpyHostToDevice, c->st));
     uint64_t o = 256;
     const Params &P = c->P;
@@ -880,6 +897,8 @@ pic_status pic_set_state(pic_ctx *c, const void *src) {
     c->np_slots = h.np_slots;
     c->cur32 = h.cur32;
     c->bw = h.bw;
+    c->win_x0 = h.win_x0;
+    c->win_t0 = h.win_t0;
     PIC_HIP(*c, hipStreamSynchronize(c->st));
     return PIC_OK;
 }
@@ -953,6 +972,8 @@ pic_status pic_state_to_fp64(const pic_ctx *src, pic_ctx *dst) {
     d.nb_slots = src->nb_slots;
     d.np_slots = src->np_slots;
     d.bw = src->bw;
+    d.win_x0 = src->win_x0;
+    d.win_t0 = src->win_t0;
     PIC_HIP(d, hipStreamSynchronize(d.st));
     return PIC_OK;
 }

@@ -42,6 +42,8 @@ struct Ctx {
     pic_undulator und;
     pic_options opt;
     double bw = 0, k_bunch_default = 0;
+    // window position (cells) at time t: win_x0 + bw (t - win_t0); k0 = its floor, at most one shift per step
+    double win_x0 = 0, win_t0 = 0;
     double beam_beta0 = 0;  // mean boosted beta_z of the beam at t' = 0
     int probe_on = 0;       // lab-frame probe armed
     double probe_t = 0, probe_k = 0;

@@ -28,13 +28,16 @@ def main(argv=None):
     ap.add_argument("--mobile-ions", type=float, default=None, metavar="MASS",
                     help="plasma ions as particles of this mass in electron masses (0: the proton's); "
                          "default: immobile ions")
+    ap.add_argument("--track-window", type=int, default=0, metavar="N",
+                    help="adjust the window speed every N steps so that the beam keeps its place in the window "
+                         "(0: the speed stays the beam's mean velocity at t' = 0)")
     a = ap.parse_args(argv)
 
     import torch
 
     import picinputs as pin
     from . import abi
-    from .sim import Sim
+    from .sim import Sim, WindowTracker
 
     w = pin.workload(a.workload)
     if a.mobile_ions is not None and w["plasma"]["n0_lab_cm3"] > 0:
@@ -55,8 +58,9 @@ def main(argv=None):
 
     def report(ms_per_step):
         d = sim.diag(mask, period)
-        keep = ("step", "t", "k0", "n_beam", "n_plasma", "beam_lost", "mean", "sigma", "umean", "usigma", "emit",
-                "b1_abs", "b2_abs", "field_energy", "kin_beam", "kin_plasma", "gauss_max", "gauss_drift", "rho_max")
+        keep = ("step", "t", "k0", "window_x", "window_beta", "n_beam", "n_plasma", "beam_lost", "mean", "sigma",
+                "umean", "usigma", "emit", "b1_abs", "b2_abs", "field_energy", "kin_beam", "kin_plasma", "gauss_max",
+                "gauss_drift", "rho_max")
         out = {k: d[k] for k in keep if k in d}
         out["ms_per_step"] = ms_per_step
         out["particle_steps_per_s"] = (d["n_beam"] + d["n_plasma"]) / (ms_per_step * 1e-3) if ms_per_step else None
@@ -66,16 +70,22 @@ def main(argv=None):
                       "precision": a.precision, "init_s": init_s,
                       "arena_GB": sim.layout.arena_bytes / 1e9}), flush=True)
     report(None)
+    tracker = WindowTracker(sim, a.track_window) if a.track_window > 0 else None
     done = 0
     while done < steps:
         k = min(a.every, steps - done)
+        if tracker:
+            k = min(k, a.track_window - done % a.track_window)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         sim.step(k)
         sim.sync()
         dt = time.perf_counter() - t1
         done += k
-        report(dt / k * 1e3)
+        if tracker and done % a.track_window == 0:
+            tracker.update()
+        if done % a.every == 0 or done == steps:
+            report(dt / k * 1e3)
     return 0
 
 

@@ -94,6 +94,10 @@ class Sim:
         _check(self.L, self.ctx, self.L.pic_timing_read(self.ctx, ms, n), "pic_timing_read")
         return list(ms), list(n)
 
+    def set_window_beta(self, beta: float):
+        """Window speed (units of c) from the current step on."""
+        _check(self.L, self.ctx, self.L.pic_set_window_beta(self.ctx, float(beta)), "pic_set_window_beta")
+
     def sync(self):
         _check(self.L, self.ctx, self.L.pic_sync(self.ctx), "pic_sync")
 
@@ -171,3 +175,34 @@ class Sim:
         g = (C.c_double * 2)(*grad)
         _check(self.L, self.ctx, self.L.pic_adjoint_step(self.ctx, C.c_void_p(lam.data_ptr()), g), "pic_adjoint_step")
         grad[0], grad[1] = g[0], g[1]
+
+
+class WindowTracker:
+    """Keeps the beam's centroid at its place in the moving window (section 3: a beam
+    that slows down, e.g. in an undulator, drifts to the back of a window that keeps
+    its speed; the window's speed is adjusted to the beam's).
+
+    Call update() every ``every`` steps.  It sets the window speed to the centroid's
+    mean velocity over the interval just ended plus the centroid's offset from its
+    place in the window divided by the interval's duration, so the next interval takes
+    the offset up; the place is where the centroid sat, relative to the window, when
+    the tracker was made."""
+
+    def __init__(self, sim: Sim, every: int):
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        d = sim.diag(abi.PIC_DIAG_MOMENTS)
+        self.sim, self.every = sim, int(every)
+        self.duration = every * derive(sim.w)["dt"]
+        self.z_prev = d["mean"][2]
+        self.place = d["mean"][2] - d["window_x"]
+
+    def update(self) -> float:
+        d = self.sim.diag(abi.PIC_DIAG_MOMENTS)
+        z = d["mean"][2]
+        velocity = (z - self.z_prev) / self.duration
+        offset = z - d["window_x"] - self.place
+        beta = min(max(velocity + offset / self.duration, 1e-6), 1.0)
+        self.sim.set_window_beta(beta)
+        self.z_prev = z
+        return beta

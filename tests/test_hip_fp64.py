@@ -247,3 +247,41 @@ def test_adjoint_gradient_matches_oracle(case, nsteps):
     assert gKg == pytest.approx(gK, rel=1e-9, abs=1e-15), (gKg, gK)
     assert gng == pytest.approx(gn, rel=1e-9, abs=1e-15), (gng, gn)
     assert abs(gK) > 1e-10 and abs(gn) > 1e-10
+
+
+def test_window_tracking_matches_oracle():
+    """The window speed adjusted every 20 steps (sim.WindowTracker on the GPU, the same policy
+    restated on the oracle's diagnostics): 400 steps of a gamma_R = 40 beam entering a helical
+    undulator, FP64 path against the oracle (window speeds to 1e-10, window positions to round-off,
+    fields to 1e-9 after the run); the
+    FP32 path's window keeps the beam within half a cell of its place too."""
+    from test_oracle_window_tracking import N_EVERY, _case
+    from paper_2411_04703_amd.sim import Sim, WindowTracker
+    w = _case()
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
+    ref = po.Sim(w, nrm)
+    w2 = pin.scaled(w)
+    w2["frame"]["window_beta"] = ref.info().bw
+    gpu = Sim(w2, nrm, precision=0, max_steps=64)
+    s32 = Sim(w2, nrm, precision=1)
+    trk, trk32 = WindowTracker(gpu, N_EVERY), WindowTracker(s32, N_EVERY)
+    dt = ref.info().dt
+    z_prev = ref.diag(1.0)["mean"][2]
+    place = z_prev - ref.info().window_x
+    for _ in range(400 // N_EVERY):
+        ref.step(N_EVERY)
+        gpu.step(N_EVERY)
+        s32.step(N_EVERY)
+        i = ref.info()
+        z = ref.diag(1.0)["mean"][2]
+        dur = N_EVERY * dt
+        ref.set_window_beta(min(max((z - z_prev) / dur + (z - i.window_x - place) / dur, 1e-6), 1.0))
+        z_prev = z
+        b64, b32 = trk.update(), trk32.update()
+        d, d32 = gpu.diag(), s32.diag()
+        assert d["k0"] == i.k0 and abs(d["window_x"] - i.window_x) <= 1e-12 * i.window_x
+        assert abs(b64 - ref.info().bw) <= 1e-10, (b64, ref.info().bw)
+        assert abs(d32["mean"][2] - d32["window_x"] - place) < 0.5
+    for f in FIELDS:  # 400 steps of round-off (the 100-step workload-0 run agrees to 1e-10)
+        assert _rel(gpu.field(f), ref.field(f)) <= 1e-9, f
+    assert ref.info().bw < 0.9
