@@ -125,3 +125,31 @@ def test_fp32_mode_adjoint_matches_fp64_mode_and_differences(K, n0):
     assert gn32 == pytest.approx(gn64, rel=1e-3), (gn32, gn64)
     fK = (_loss(w, nrm, 48, 12, K * (1 + H), n0) - _loss(w, nrm, 48, 12, K * (1 - H), n0)) / (2 * H)
     assert gK32 == pytest.approx(fK, rel=1e-3)
+
+
+def _golden():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_subcase_500.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-9), (1, 1e-3)])
+def test_adjoint_subcase_500_steps_against_oracle(precision, bar):
+    """The 16x16x64 subcase of the adjoint workload over 500 steps with a checkpoint every 50
+    (ten recomputed segments), against the oracle's stored-state adjoint of the same run
+    (tests/golden/adjoint_subcase_500.json, written by the oracle alone; there the oracle's
+    adjoint agrees with its complex-step derivatives to 3e-12).  FP64 mode: 1e-9 relative.
+    FP32 mode (the adjoint linearised about the FP32 trajectory): 1e-3 relative, the FP32
+    path's stated bar."""
+    from paper_2411_04703_amd.autograd import bunching_grad
+    g = _golden()
+    w = pin.adjoint_subcase()
+    w["frame"]["window_beta"] = g["window_beta"]
+    nrm = pin.beam_normals(w["beam"]["n_macro"], g["seed"])
+    L, gK, gn = bunching_grad(w, nrm, g["nsteps"], every=50, bunch_period=g["bunch_period_cells"],
+                              precision=precision)
+    print("adjoint 500", precision, L, gK, gn, g["L"], g["K_dL_dK"], g["n0_dL_dn0"], flush=True)
+    assert L == pytest.approx(g["L"], rel=bar)
+    assert gK == pytest.approx(g["K_dL_dK"], rel=bar)
+    assert gn == pytest.approx(g["n0_dL_dn0"], rel=bar)

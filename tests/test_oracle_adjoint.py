@@ -108,3 +108,17 @@ def test_adjoint_matches_central_differences():
             vals.append(po.loss_bunching(ww, nrm, N, KB)[0])
         fd = (vals[0] - vals[1]) / (2 * h)  # = p0 dL/dp0
         assert abs(fd - g) < 1e-4 * abs(g), (key, fd, g)
+
+
+def test_stored_500_step_adjoint_agrees_with_complex_step():
+    """The oracle's 500-step adjoint of the 16x16x64 subcase (checkpointed every step, the
+    reference for the GPU's checkpointed adjoint) agrees with the complex-step derivative of
+    the oracle's forward run, computed by the same script, to 1e-11 relative."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_subcase_500.json")
+    g = json.load(open(path))
+    assert g["nsteps"] == 500
+    for a, b in (("K_dL_dK", "complex_step_K_dL_dK"), ("n0_dL_dn0", "complex_step_n0_dL_dn0")):
+        assert abs(g[a]) > 1e-2 * g["L"]
+        assert abs(g[a] - g[b]) <= 1e-11 * abs(g[b]), (a, g[a], g[b])
