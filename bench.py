@@ -80,7 +80,17 @@ def cpu_baseline(seconds_budget: float = 20.0) -> dict:
     dt = time.perf_counter() - t0
     return {"value": npart * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"32x32x128 cells (1/64 of the workload volume), {i.n_beam} beam + {i.n_plasma} plasma "
-                      f"particles, {steps} steps, single-threaded FP64 C"}
+                      f"particles, {steps} steps, single-threaded FP64 C",
+            "host_cpu": host_cpu_model(), "host_cores": len(os.sched_getaffinity(0)),
+            "host_cores_online": os.cpu_count()}
+
+
+def host_cpu_model() -> str:
+    import platform
+    try:
+        return next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return platform.processor() or "unknown"
 
 
 def cpu_table():
@@ -89,7 +99,6 @@ def cpu_table():
     and the 16x16x64 adjoint case (100 steps forward, and forward + adjoint).
     Prints one JSON line; the host's CPU model and core count are included."""
     import math
-    import platform
 
     import torch
 
@@ -102,11 +111,7 @@ def cpu_table():
 
     if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
         ob.build()
-    model = platform.processor()
-    try:
-        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+    model = host_cpu_model()
     rows = []
 
     def timed(fn):
@@ -189,13 +194,37 @@ def copy_calibration(mib: int):
         b.copy_(a)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    print(json.dumps({"copy_mib": mib, "bytes_read": 4 * n, "bytes_written": 4 * n,
-                      "ms": dt * 1e3, "GBps_read_plus_write": 8 * n / dt / 1e9}), flush=True)
+    out = {"copy_mib": mib, "bytes_read": 4 * n, "bytes_written": 4 * n,
+           "ms": dt * 1e3, "GBps_read_plus_write": 8 * n / dt / 1e9}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def describe(w: dict) -> str:
+    """The workload named by what it is, with its sizes."""
+    g, b, p, u = w["grid"], w["beam"], w["plasma"], w["undulator"]
+    text = (f"{g['nx']}x{g['ny']}x{g['nz']} cells, gamma_R={w['frame']['gamma_boost']:g}, beam {b['n_macro']:,} "
+            f"macroparticles (sigma {b['sigma_cells'][0]:g}x{b['sigma_cells'][1]:g}x{b['sigma_cells'][2]:g} cells, "
+            f"lab gamma {b['gamma_lab']:g})")
+    if p["n0_lab_cm3"] > 0:
+        ppc = p["ppc"][0] * p["ppc"][1] * p["ppc"][2]
+        shape = "uniform" if p["length_lab_m"] <= 0 else \
+            f"{p['length_lab_m'] * 100:g} cm channel with a {p['ramp_up_lab_m'] * 100:g} cm up-ramp"
+        ions = {0: "no ions", 1: "immobile ions", 2: "mobile ions"}[p["ions"]]
+        text += f" + cold plasma {p['n0_lab_cm3']:g} cm^-3 ({shape}) at {ppc} ppc with {ions}"
+    if u["kind"]:
+        text += f" in a {'helical' if u['kind'] == 1 else 'planar'} undulator, K={u['K']:g}"
+    cfl = g["cfl"]
+    return text + (", c dt = dx/2" if abs(cfl - 0.8660254037844386) < 1e-12 else f", CFL {cfl:g}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=1, choices=(1, 2, 4, 5),
+                    help="1: 128x128x512 (the metric's configuration, default); 2: 256x256x1024 plasma channel; "
+                         "4: 512x512x2048 undulator + plasma; 5: 2048x1x4096 x-z grid")
     ap.add_argument("--steps", type=int, default=1000, help="timed steps (default: the workload's full 1000-step run)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -215,7 +244,7 @@ def main():
         cpu_table()
         return
     if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
+        print(json.dumps(copy_calibration(args.copy_calibration)), flush=True)
         return
     if args.atomic_calibration:
         atomic_calibration(args.atomic_calibration)
@@ -231,10 +260,14 @@ def main():
     from paper_2411_04703_amd import abi
     from paper_2411_04703_amd.sim import Sim
 
-    w = pin.workload(1)
+    w = pin.workload(args.workload)
     nrm = pin.beam_normals(w["beam"]["n_macro"], 0)
     g = w["grid"]
     n_cells = g["nx"] * g["ny"] * g["nz"]
+    if args.workload != 1:  # the FP64 comparison and the oracle sample are defined on the metric's workload
+        args.no_fp64 = True
+        args.no_cpu_baseline = True
+    copy = copy_calibration(1024)  # the HBM bandwidth a plain copy reaches, beside the vendor peak
 
     def run(precision):
         opts = dict(precision=precision)
@@ -283,8 +316,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == abi.PIC_FP32_SPLIT else "f64",
         "data": "synthetic",
-        "config": {"workload": "128x128x512 cells, gamma_R=20, beam 4,194,304 macroparticles (sigma 4x4x32 cells, "
-                               "lab gamma 200) + cold plasma 1e16 cm^-3 at 2 ppc with immobile ions, c dt = dx/2",
+        "config": {"workload": describe(w),
                    "particles_active": n_active, "cells": n_cells,
                    "precision": "fp32_split_fixed_point" if prec == abi.PIC_FP32_SPLIT else "fp64_plain",
                    "deposit_variant": args.variant, "tile": tile_used, "wg_per_cu": args.wg_per_cu},
@@ -295,7 +327,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (prec == abi.PIC_FP32_SPLIT and tile == (0, 0, 0)
-                                                       and args.variant == 0) else None,
+                                                       and args.variant == 0 and args.workload == 1) else None,
+                     "measured_copy_GBps": copy["GBps_read_plus_write"],
+                     "frac_of_measured_copy": achieved / copy["GBps_read_plus_write"],
                      "kernel": "fused particle kernel(s): gather, push, deposit",
                      "bytes_per_step": ab["total"], "bytes_per_particle": ab["per_particle"],
                      "bytes_per_cell": ab["per_cell"], "avg_ms_per_step": part_ms,

@@ -171,41 +171,68 @@ def test_workload1_fp32_tracks_fp64_at_full_size():
         assert err <= 1e-4 * max(total, gross), (f, err, total, gross)
 
 
+def _ulp_perturbed(sim, rng):
+    """Every coordinate of every live particle of an FP64 state moved by one FP32 ulp, up or down
+    at random: positions by the ulp of their in-cell offset (how the FP32 path stores them),
+    momenta by the ulp of their FP32 value."""
+    from paper_2411_04703_amd import abi
+    for which, alive in ((abi.PIC_A_BEAM, abi.PIC_A_BEAM_ALIVE), (abi.PIC_A_PLASMA, abi.PIC_A_PLASMA_ALIVE)):
+        a = sim.read(which).cpu().numpy()
+        live = sim.read(alive).cpu().numpy() == 1
+        n = int(live.sum())
+        if n == 0:
+            continue
+        for r in range(3):
+            off = a[r, live] - np.floor(a[r, live])
+            a[r, live] += rng.choice((-1.0, 1.0), n) * np.spacing(off.astype(np.float32)).astype(np.float64)
+        for r in range(3, 6):
+            u = np.abs(a[r, live]).astype(np.float32)
+            a[r, live] += rng.choice((-1.0, 1.0), n) * np.spacing(u).astype(np.float64)
+        sim.write(which, a)
+
+
+@pytest.mark.timeout(900)
 def test_workload1_full_run_fp32_within_stated_tolerance():
-    """After the workload's full 1000 steps the FP32 path's beam moments and
-    bunching factor agree with the FP64 path's (which follows the oracle to
-    1e-12 per step at small sizes) within the stated tolerance: per quantity,
-    max(2e-3 relative, 3x the spread between two FP64 runs whose initial beam
-    phase space differs by one FP32 rounding); the bunching factor, which is at
-    noise level here, absolutely within max(1e-6, 3x that spread).  The single
-    initial rounding spreads the FP64 moments by < 3.5e-4; the FP32 run rounds
-    every step, and its transverse sigma lands near 1e-3 after the 1000 steps
-    of the pinched beam, hence a floor of twice that."""
+    """After the workload's full 1000 steps the FP32 path's beam moments agree with the FP64
+    path's (which follows the oracle to 1e-12 per step at small sizes) within the tolerance stated
+    before the measurement: per quantity, max(1e-3 relative, 3x the spread of four FP64 runs
+    whose initial particles -- beam and plasma -- are each moved by one FP32 ulp per coordinate,
+    independently and at random).  The spread measures how far the discretised system itself
+    carries such rounding-sized differences in 1000 steps; the FP32 run makes them at every
+    step.  The bunching factor, at noise level here, absolutely within max(1e-6, 3x its
+    spread)."""
     from paper_2411_04703_amd.sim import Sim
     nsteps = W["steps"]
     nrm = pin.beam_normals(W["beam"]["n_macro"], 0)
-    nrm_p = nrm.copy()
-    nrm_p *= 1.0 + 2.0 ** -24  # every draw: one FP32 rounding of the initial positions and momenta
-    out = []
-    for prec, g in ((1, nrm), (0, nrm), (0, nrm_p)):
-        s = Sim(W, g, precision=prec, **({} if prec else {"max_steps": 64}))
+    s = Sim(W, nrm, precision=1)
+    s.step(nsteps)
+    d32 = s.diag()
+    del s
+    d64p = []
+    for seed in range(5):  # seed 0: unperturbed
+        s = Sim(W, nrm, precision=0, max_steps=64)
+        if seed:
+            _ulp_perturbed(s, np.random.default_rng(seed))
         s.step(nsteps)
-        out.append(s.diag())
+        d64p.append(s.diag())
         del s
-    d32, d64, d64p = out
+        print("fp64 run", seed, "done", flush=True)
+    d64 = d64p[0]
     assert d32["n_beam"] == d64["n_beam"] and d32["n_plasma"] == d64["n_plasma"]
     report = {}
     for k in ("mean", "sigma", "usigma", "emit"):
-        a, b, c = (np.asarray(d[k], dtype=float) for d in (d32, d64, d64p))
+        b = np.asarray(d64[k], dtype=float)
         scale = np.maximum(np.abs(b), 1e-300)
-        err, spread = np.abs(a - b) / scale, np.abs(c - b) / scale
-        tol = np.maximum(2e-3, 3.0 * spread)
-        report[k] = (err.tolist(), tol.tolist())
-    print("full-run tolerance report", report, flush=True)
-    for k, (err, tol) in report.items():
+        err = np.abs(np.asarray(d32[k], dtype=float) - b) / scale
+        spread = np.max([np.abs(np.asarray(d[k], dtype=float) - b) / scale for d in d64p[1:]], axis=0)
+        tol = np.maximum(1e-3, 3.0 * spread)
+        report[k] = (err.tolist(), spread.tolist(), tol.tolist())
+    print("full-run tolerance report (error, spread, tolerance)", report, flush=True)
+    eb = abs(d32["b1_abs"] - d64["b1_abs"])
+    sb = max(abs(d["b1_abs"] - d64["b1_abs"]) for d in d64p[1:])
+    print("b1_abs", eb, sb, max(1e-6, 3.0 * sb), flush=True)
+    for k, (err, _, tol) in report.items():
         assert np.all(np.asarray(err) <= np.asarray(tol)), (k, err, tol)
-    eb, sb = abs(d32["b1_abs"] - d64["b1_abs"]), abs(d64p["b1_abs"] - d64["b1_abs"])
-    print("b1_abs", eb, max(1e-6, 3.0 * sb), flush=True)
     assert eb <= max(1e-6, 3.0 * sb), (eb, sb)
 
 
@@ -231,3 +258,25 @@ def test_workload1_stays_stable_over_two_and_a_half_runs():
     assert fe[-1] < 0.8 * peak, fe
     # the beam is still there (a percent of its tail has left the window by now)
     assert s.diag()["n_beam"] > 0.98 * W["beam"]["n_macro"]
+
+
+def test_workload1_front_face_changes_no_result():
+    """The moving window's front face holds the tangential E at zero.  Over the workload's 1000
+    steps the same beam and plasma in a window that reaches 64 cells further ahead (same particles,
+    same distance from the back face) end with the same beam diagnostics: the FP32 path is
+    deterministic, so any difference is the face's doing."""
+    import copy
+    nsteps = W["steps"]
+    w2 = copy.deepcopy(W)
+    w2["grid"]["nz"] = W["grid"]["nz"] + 64
+    out = []
+    for w in (W, w2):
+        s = _gpu(1, w=w)
+        s.step(nsteps)
+        out.append(s.diag())
+        del s
+    a, b = out
+    assert a["n_beam"] == b["n_beam"] == W["beam"]["n_macro"]
+    for k in ("mean", "sigma", "usigma", "emit"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-6, atol=1e-12, err_msg=k)
+    assert abs(a["b1_abs"] - b["b1_abs"]) < 1e-9
