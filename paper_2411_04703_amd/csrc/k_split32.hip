@@ -89,6 +89,10 @@ template <typename T> __device__ inline __attribute__((address_space(1))) T *gbl
     return (__attribute__((address_space(1))) T *)p;
 }
 
+// Hides v's value from the optimiser: what is computed from it is neither folded into
+// constants nor hoisted out of the work-item loop (and kept live, or spilled, across it).
+__device__ inline void opaque(int &v) { asm volatile("" : "+v"(v)); }
+
 // Reserve one slot per active lane in bin `key` of cnt; lanes with equal keys
 // share one atomic.  Returns the rank within the bin (-1 for inactive lanes).
 // Called by every lane of the wave.
@@ -223,6 +227,33 @@ __device__ inline void store_in_bin(const OutStore &O, bool active, int r, int b
     if (id_out) gbl(id_out)[s] = id;
 }
 
+// store_in_bin with the bin's first slot b0 and capacity cap already loaded
+__device__ inline void store_at(const OutStore &O, bool active, int r, int64_t b0, int64_t cap, int cell,
+                                const float o[3], const float u[3], float w, int32_t *flags, int32_t *id_out, int id) {
+    if (!active) return;
+    int64_t s;
+    if (r < cap) {
+        s = b0 + r;
+    } else {
+        int k = atomicAdd(O.ovf, 1);
+        if (k >= O.ovf_cap) {
+            atomicOr(flags, DFLAG_BIN_LOST);
+            return;
+        }
+        s = O.bin_slots + k;
+    }
+    const Part32 &b = O.buf;
+    gbl(b.cell)[s] = cell;
+    gbl(b.ox)[s] = o[0];
+    gbl(b.oy)[s] = o[1];
+    gbl(b.oz)[s] = o[2];
+    gbl(b.ux)[s] = u[0];
+    gbl(b.uy)[s] = u[1];
+    gbl(b.uz)[s] = u[2];
+    gbl(b.w)[s] = w;
+    if (id_out) gbl(id_out)[s] = id;
+}
+
 __device__ inline int bin_of(const Params &P, int i, int j, int l) {
     return (i >> P.lgx) + P.ntx * ((j >> P.lgy) + P.nty * (l >> P.lgz));
 }
@@ -255,9 +286,8 @@ __device__ inline int bin_count(const int64_t *off, const int32_t *cnt, int b) {
 }
 
 // fixed-point value rint(x y) of one current contribution, rounded to nearest
-// even: x y is the exact product of an FP32 factor and an FP32 factor scaled by
-// 2^f (at most 48 significant bits, so the FMA rounds once), and adding
-// 1.5 * 2^52 leaves the integer in the low mantissa bits whenever
+// even: the FMA forms x y exactly and rounds it once together with the added
+// 1.5 * 2^52, which leaves the integer in the low mantissa bits whenever
 // |x y| < 2^51, which fixed_ok() has established for the whole particle
 __device__ inline long long to_fixed(double x, double y) {
     const double magic = 6755399441055744.0;  // 1.5 * 2^52
@@ -385,8 +415,9 @@ __device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
 //   J_c(m, a, b) = f P_c[m] A_c[a][b],  P_c[m] = sum_{m' <= m} DS_c[m'],
 //   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3),
 // and P_c[2] = -DS_c[3] (the DS sum to zero), exactly zero without a crossing.
-// The value converted is the exact product of the FP32 numbers f A_c[a][b]
-// and P_c[m] 2^fs.
+// f P_c[m] 2^fs is exact in FP64 (a product of two FP32 numbers and a power of
+// two), so each value converted is the exact product of the three FP32 factors
+// f, P_c[m] and A_c[a][b], rounded once to the fixed point.
 // DEP 0 visits nonzero contributions only (one branch each); DEP 1 visits all
 // 48 of a component that moves along its axis; DEP 2 leaves out the window's
 // last node along an axis (m = 2, a = 3 or b = 3) when no lane of the wave
@@ -400,9 +431,10 @@ __device__ inline void esk_component(const Esk &e, float f, double fscale, F &&f
     Pm[1] = Pm[0] + e.DS[C][1];
     Pm[2] = -e.DS[C][3];
     if (DEP != 0 && Pm[0] == 0.0f && Pm[1] == 0.0f && Pm[2] == 0.0f) return;
+    const double fs = fscale * (double)f;  // exact: f times a power of two
     double Pd[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) Pd[m] = (double)Pm[m] * fscale;
+    for (int m = 0; m < 3; ++m) Pd[m] = (double)Pm[m] * fs;  // exact: 24 x 24 significant bits
     float ub[4], vb[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -412,22 +444,15 @@ __device__ inline void esk_component(const Esk &e, float f, double fscale, F &&f
     if (DEP == 2) {
         const bool m2 = __any(e.cross & (1 << C)), a3 = __any(e.cross & (1 << CA)), b3 = __any(e.cross & (1 << CB));
 #pragma unroll
-        for (int mm = 0; mm < 2; ++mm) {
-            if (mm == 1 && !m2) break;
+        for (int a = 0; a < 4; ++a) {
+            if (a == 3 && !a3) break;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                if (a == 3 && !a3) break;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (b == 3 && !b3) break;
-                    const double fa = (double)(f * fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]));
-                    if (mm == 0) {
-                        fn(C, 0, a, b, to_fixed(fa, Pd[0]));
-                        fn(C, 1, a, b, to_fixed(fa, Pd[1]));
-                    } else {
-                        fn(C, 2, a, b, to_fixed(fa, Pd[2]));
-                    }
-                }
+            for (int b = 0; b < 4; ++b) {
+                if (b == 3 && !b3) break;
+                const double A = (double)fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
+                fn(C, 0, a, b, to_fixed(A, Pd[0]));
+                fn(C, 1, a, b, to_fixed(A, Pd[1]));
+                if (m2) fn(C, 2, a, b, to_fixed(A, Pd[2]));
             }
         }
         return;
@@ -438,10 +463,10 @@ __device__ inline void esk_component(const Esk &e, float f, double fscale, F &&f
         for (int b = 0; b < 4; ++b) {
             float A = fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
             if (DEP == 0 && A == 0.0f) continue;
-            const double fa = (double)(f * A);
+            const double Ad = (double)A;
 #pragma unroll
             for (int m = 0; m < 3; ++m)
-                if (DEP != 0 || Pm[m] != 0.0f) fn(C, m, a, b, to_fixed(fa, Pd[m]));
+                if (DEP != 0 || Pm[m] != 0.0f) fn(C, m, a, b, to_fixed(Ad, Pd[m]));
         }
 }
 
@@ -526,9 +551,23 @@ struct GlobalField {
         half_curl_b(&ex[0][0][0], &ey[0][0][0], &ez[0][0][0], 1, 2, 4, l == P->nz - 1, hb, dB);
         return e(comp, i, j, l) + dB[comp - 3];
     }
+    struct Plane {
+        const GlobalField *g;
+        int comp, x, y, z;
+        __device__ float operator()(int a, int b) const { return g->at(comp, x + a, y + b, z); }
+    };
+    struct Node {
+        const GlobalField *g;
+        int comp, x, y, z;
+        __device__ Plane plane(int c) const { return Plane{g, comp, x, y, z + c}; }
+    };
+    __device__ Node node(int comp, int x, int y, int z) const { return Node{this, comp, x, y, z}; }
 };
 
-// six Yee components with quadratic shapes; (x0, y0, z0) = cell relative to the accessor's origin
+// six Yee components with quadratic shapes; (x0, y0, z0) = cell relative to the accessor's origin.
+// Per component the 27-node sum is taken as nested one-dimensional sums: along x for each of the
+// nine rows, along y for each of the three planes, then along z.  Both accessors (the LDS box of
+// the tiled path and the global arrays of the untiled one) see the same operations in the same order.
 template <class FA> __device__ inline void gather6(const FA &fa, const float o[3], int x0, int y0, int z0, float EB[6]) {
     float wI[3][3], wH[3][3];
     int bI[3], bH[3];
@@ -546,23 +585,17 @@ template <class FA> __device__ inline void gather6(const FA &fa, const float o[3
                   sz = comp == 2 || comp == 3 || comp == 4;
         const float *wx = sx ? wH[0] : wI[0], *wy = sy ? wH[1] : wI[1], *wz = sz ? wH[2] : wI[2];
         const int bx = sx ? bH[0] : bI[0], by = sy ? bH[1] : bI[1], bz = sz ? bH[2] : bI[2];
-        float acc = 0.0f;
+        const auto box = fa.node(comp, bx, by, bz);  // plane c's values are box.plane(c)(a, b), a, b in 0..2
+        float pz[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            // the 9 loads of a plane first, so that one wait covers them
-            float v[9];
+            const auto pl = box.plane(c);
+            float py[3];
 #pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) v[b * 3 + a] = fa.at(comp, bx + a, by + b, bz + c);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const float *row = v + b * 3;
-                float r = fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0]));
-                acc = fmaf(wy[b] * wz[c], r, acc);
-            }
+            for (int b = 0; b < 3; ++b) py[b] = fmaf(wx[2], pl(2, b), fmaf(wx[1], pl(1, b), wx[0] * pl(0, b)));
+            pz[c] = fmaf(wy[2], py[2], fmaf(wy[1], py[1], wy[0] * py[0]));
         }
-        EB[comp] = acc;
+        EB[comp] = fmaf(wz[2], pz[2], fmaf(wz[1], pz[1], wz[0] * pz[0]));
         __builtin_amdgcn_sched_barrier(0);  // components do not interleave (register pressure)
     }
 }
@@ -641,10 +674,74 @@ template <int TX, int TY, int TZ> struct TileGeom {
 template <class G> struct LdsBoxT {
     const float *F;  // 3 E boxes of G::NF floats, then 3 B boxes of G::NE; box index of (half-)node k
                      // (relative to t0) is k + 1
-    __device__ float at(int comp, int x, int y, int z) const {
-        return comp < 3 ? F[comp * G::NF + (x + 1) + G::FX * ((y + 1) + G::FY * (z + 1))]
-                        : F[3 * G::NF + (comp - 3) * G::NE + (x + 1) + G::EX * ((y + 1) + G::EY * (z + 1))];
+    // the 27 nodes from (x, y, z) on of one component, plane by plane: one LDS address per plane
+    // (kept in its own register, so that the nine reads of a plane, paired or not, take their
+    // node offsets as immediates), sy and sz compile-time once inlined (the component is)
+    using LdsPtr = const __attribute__((address_space(3))) float *;
+    struct Plane {
+        LdsPtr p;
+        int sy;
+        __device__ float operator()(int a, int b) const { return p[a + sy * b]; }
+    };
+    struct Node {
+        LdsPtr L;
+        int idx, sy, sz;
+        __device__ Plane plane(int c) const {
+            int k = idx + sz * c;
+            opaque(k);
+            return Plane{L + k, sy};
+        }
+    };
+    __device__ Node node(int comp, int x, int y, int z) const {
+        const LdsPtr L = (LdsPtr)F;
+        return comp < 3 ? Node{L, comp * G::NF + (x + 1) + G::FX * ((y + 1) + G::FY * (z + 1)), G::FX, G::FX * G::FY}
+                        : Node{L, 3 * G::NF + (comp - 3) * G::NE + (x + 1) + G::EX * ((y + 1) + G::EY * (z + 1)),
+                               G::EX, G::EX * G::EY};
     }
+};
+
+// A particle record as loaded; it is unpacked when its round starts, so that
+// the loads of the next round are in flight while the current round computes.
+struct PRaw {
+    int cell;
+    float o[3], u[3], w;
+    int id;
+};
+
+__device__ inline void load_raw(const Part32 &in, int64_t s, PRaw &r, const int32_t *id_in) {
+    r.cell = gbl(in.cell)[s];
+    r.o[0] = gbl(in.ox)[s];
+    r.o[1] = gbl(in.oy)[s];
+    r.o[2] = gbl(in.oz)[s];
+    r.u[0] = gbl(in.ux)[s];
+    r.u[1] = gbl(in.uy)[s];
+    r.u[2] = gbl(in.uz)[s];
+    r.w = gbl(in.w)[s];
+    r.id = id_in ? gbl(id_in)[s] : 0;
+}
+
+__device__ inline void unpack_raw(const Params &P, const PRaw &r, PState &q) {
+    unpack_cell(P, r.cell, q.i, q.j, q.l);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        q.o[d] = r.o[d];
+        q.u[d] = r.u[d];
+    }
+    q.w = r.w;
+    q.id = r.id;
+}
+
+// One float from global memory straight into LDS (no register on the way):
+// lane L of the wave writes dst_wave[L]; dst_wave is the same for the whole wave.
+__device__ inline void lds_load(const float *src, float *dst_wave) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)dst_wave, 4, 0, 0);
+}
+
+// one work item as the step kernel sees it (wave-uniform values)
+struct ItemT {
+    int sp, bin, start, end, t0x, t0y, t0z;
+    int64_t b0;
 };
 
 template <int TX, int TY, int TZ, int DEP, bool REC>
@@ -657,183 +754,251 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
     __shared__ int s_item, s_qstart[9];
     const int tid = threadIdx.x;
     if (tid <= nslab) s_qstart[tid] = qstart[tid];  // constant during the launch
-    __syncthreads();
     float *Fs = (float *)smem;
+    float *Bs = Fs + 3 * G::NF;
     long long *Js = (long long *)(smem + G::EBYTES);
     double *tabA = (double *)(Js + G::NJ);
     float *tabC = (float *)(tabA + G::NTAB), *tabS = tabC + G::NTAB;
     const float *F6[6] = {f.E[0], f.E[1], f.E[2], f.B[0], f.B[1], f.B[2]};
     const float hb = (float)(0.5 * P.dt);
-    // slab queue of this workgroup's XCD first, then the others' (work stealing)
-    int q = (int)(blockIdx.x % (unsigned)nslab), hops = 0;
+    for (int k = tid; k < G::NJ; k += SST) Js[k] = 0;  // cleared once; every flush clears what it reads
+    __syncthreads();
 
-    for (;;) {
-        if (tid == 0) {
-            int it = -1;
-            while (hops < nslab) {
-                const int k = s_qstart[q] + atomicAdd(&qnext[q * QPAD], 1);
-                if (k < s_qstart[q + 1]) {
-                    it = k;
-                    break;
-                }
-                q = q + 1 == nslab ? 0 : q + 1;
-                ++hops;
-            }
-            s_item = it;
+    // Work queues: one per z slab of bins; this workgroup's XCD's slab first, then the others'
+    // (work stealing).  Thread 0 keeps one claim on queue q in flight: the counter value for
+    // the item after the current one, claimed when the current one starts and resolved when it
+    // ends, so the atomic's round trip is hidden behind the item's work.
+    int q = (int)(blockIdx.x % (unsigned)nslab), hops = 0, claim = 0;
+    auto resolve = [&]() -> int {  // thread 0: the claimed item, or the next queue's, or -1
+        int k = s_qstart[q] + claim;
+        while (k >= s_qstart[q + 1]) {
+            q = q + 1 == nslab ? 0 : q + 1;
+            if (++hops >= nslab) return -1;
+            k = s_qstart[q] + atomicAdd(&qnext[q * QPAD], 1);
         }
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar loads of the item and its descriptor
-        __syncthreads();
-        if (item < 0) break;
+        return k;
+    };
+    auto decode = [&](int item) -> ItemT {
+        ItemT I;
         const int4 it = items[item];
-        const int sp = __builtin_amdgcn_readfirstlane(it.x), bin = __builtin_amdgcn_readfirstlane(it.y),
-                  start = __builtin_amdgcn_readfirstlane(it.z), cnt = __builtin_amdgcn_readfirstlane(it.w);
-        // descriptors by value (kernel arguments): their pointers are known to be global, and
-        // indexing with the uniform species loads just this item's descriptor with scalar loads
-        const SpeciesIO &IO = iop.s[sp];
-
-        if (bin < 0) continue;  // overflow tails: k_split_overflow
-
-        const int t0x = (bin % P.ntx) * TX, t0y = ((bin / P.ntx) % P.nty) * TY, t0z = (bin / (P.ntx * P.nty)) * TZ;
-        const int64_t b0 = gbl(IO.in_off)[bin];
-        const int end = min(cnt, start + CH);
-        // stage E^n and B^(n-1/2): box node (a, b, c) <-> absolute node (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)
-        for (int k = tid; k < G::NF; k += SST) {
-            const int bc = k / G::FX, a = k - bc * G::FX, c = bc / G::FY, b = bc - c * G::FY;
-            int l = t0z - 1 + c;
-            l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
-            const int64_t o = near_cell<TY == 1>(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+        I.sp = __builtin_amdgcn_readfirstlane(it.x);
+        I.bin = __builtin_amdgcn_readfirstlane(it.y);
+        I.start = __builtin_amdgcn_readfirstlane(it.z);
+        const int cnt = __builtin_amdgcn_readfirstlane(it.w);
+        I.end = min(cnt, I.start + CH);
+        const int bin = I.bin < 0 ? 0 : I.bin;
+        I.t0x = (bin % P.ntx) * TX;
+        I.t0y = ((bin / P.ntx) % P.nty) * TY;
+        I.t0z = (bin / (P.ntx * P.nty)) * TZ;
+        I.b0 = I.bin < 0 ? 0 : gbl(iop.s[I.sp].in_off)[bin];
+        return I;
+    };
+    // E^n and B^(n-1/2) of an item's tile (box node (a, b, c) <-> absolute node
+    // (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)) and its undulator phase table, loaded straight
+    // into LDS; nothing waits for them until the next barrier at the top of the item loop
+    auto stage = [&](const ItemT &I) {
+        constexpr int NFI = (G::NF + SST - 1) / SST, NEI = (G::NE + SST - 1) / SST;
+        const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) Fs[q * G::NF + k] = F6[q][o];
-        }
-        float *Bs = Fs + 3 * G::NF;
-        for (int k = tid; k < G::NE; k += SST) {
-            const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
-            int l = t0z - 1 + c;
-            l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);
-            const int64_t o = near_cell<TY == 1>(P, t0x - 1 + a, t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+        for (int r = 0; r < NFI; ++r) {
+            int k = tid + r * SST;
+            opaque(k);
+            if (k < G::NF) {
+                const int bc = k / G::FX, a = k - bc * G::FX, c = bc / G::FY, b = bc - c * G::FY;
+                int l = I.t0z - 1 + c;
+                l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
+                const int64_t o = near_cell<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
-            for (int q = 0; q < 3; ++q) Bs[q * G::NE + k] = F6[3 + q][o];
-        }
-        __syncthreads();
-        // B^n = B^(n-1/2) - (dt/2) curl E^n on the B box (the first half of the Yee B update)
-        for (int k = tid; k < G::NE; k += SST) {
-            const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
-            const float *ex = Fs + a + G::FX * (b + G::FY * c), *ey = ex + G::NF, *ez = ey + G::NF;
-            float B3[3];
-            half_curl_b(ex, ey, ez, 1, G::FX, G::FX * G::FY, t0z - 1 + c == P.nz - 1, hb, B3);
-            Bs[k] += B3[0];
-            Bs[G::NE + k] += B3[1];
-            Bs[2 * G::NE + k] += B3[2];
-        }
-        for (int k = tid; k < G::NJ; k += SST) Js[k] = 0;
-        if (P.und_kind)
-            for (int k = tid; k < G::NTAB; k += SST) {  // planes t0z - 1 ...: table entries t0z ...
-                tabA[k] = gtabA[t0z + k];
-                tabC[k] = gtabC[t0z + k];
-                tabS[k] = gtabS[t0z + k];
+                for (int qq = 0; qq < 3; ++qq) lds_load(F6[qq] + o, Fs + qq * G::NF + r * SST + wbase);
             }
-        __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < NEI; ++r) {
+            int k = tid + r * SST;
+            opaque(k);
+            if (k < G::NE) {
+                const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
+                int l = I.t0z - 1 + c;
+                l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);
+                const int64_t o = near_cell<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+#pragma unroll
+                for (int qq = 0; qq < 3; ++qq) lds_load(F6[3 + qq] + o, Bs + qq * G::NE + r * SST + wbase);
+            }
+        }
+        static_assert(G::NTAB <= SST, "one table entry per thread");
+        if (P.und_kind && tid < G::NTAB) {  // planes t0z - 1 ...: table entries t0z ...
+            int k = tid;
+            opaque(k);
+            tabA[k] = gtabA[I.t0z + k];
+            tabC[k] = gtabC[I.t0z + k];
+            tabS[k] = gtabS[I.t0z + k];
+        }
+    };
 
-        const LdsBoxT<G> box{Fs};
-        for (int base = start; base < end; base += SST) {
-            // pushed: advanced (deposits its current); act: still in the band (appended)
-            bool act = base + tid < end, pushed = false;
-            PState q;
-            float X0[3] = {0.0f, 0.0f, 0.0f}, X1[3] = {0.0f, 0.0f, 0.0f}, fq = 0.0f;
-            int li = 0, lj = 0, lk = 0;
-            if (act) {
-                load_particle(IO.in, b0 + base + tid, P, q, REC ? iop.id[sp].in : nullptr);
-                li = q.i - t0x;
-                lj = q.j - t0y;
-                lk = q.l - t0z;
-                const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
-                                    q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
-                                    q.o[2] >= 0.0f && q.o[2] < 1.0f;
-                if (!inside) {
-                    // cannot happen: every binned particle was appended to the bin of its cell
-                    atomicOr(flags, DFLAG_BIN_LOST);
-                    act = false;
-                } else {
-                    float EB[6];
-                    gather6(box, q.o, li, lj, lk, EB);
-                    if (!advance(P, EB, P.und_kind != 0, tabA[lk + 1], tabC[lk + 1], tabS[lk + 1], q, X1)) {
-                        atomicOr(flags, DFLAG_NONFINITE);
+    if (tid == 0) {
+        claim = atomicAdd(&qnext[q * QPAD], 1);
+        const int first = resolve();
+        s_item = first;
+    }
+    __syncthreads();
+    int cur = __builtin_amdgcn_readfirstlane(s_item);
+    ItemT I{};
+    PRaw nx;  // this thread's particle of the next round
+    if (cur >= 0) {
+        I = decode(cur);
+        if (I.bin >= 0) {
+            stage(I);
+            if (I.start + tid < I.end) load_raw(iop.s[I.sp].in, I.b0 + I.start + tid, nx, REC ? iop.id[I.sp].in : nullptr);
+        }
+    }
+
+    while (cur >= 0) {
+        // the staged boxes have landed, and the previous item's flush has cleared the current boxes
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const SpeciesIO &IO = iop.s[I.sp];
+        if (I.bin >= 0) {  // overflow tails (bin < 0) are k_split_overflow's
+            // B^n = B^(n-1/2) - (dt/2) curl E^n on the B box (the first half of the Yee B update)
+            for (int k = tid; k < G::NE; k += SST) {
+                const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
+                const float *ex = Fs + a + G::FX * (b + G::FY * c), *ey = ex + G::NF, *ez = ey + G::NF;
+                float B3[3];
+                half_curl_b(ex, ey, ez, 1, G::FX, G::FX * G::FY, I.t0z - 1 + c == P.nz - 1, hb, B3);
+                Bs[k] += B3[0];
+                Bs[G::NE + k] += B3[1];
+                Bs[2 * G::NE + k] += B3[2];
+            }
+        }
+        __syncthreads();  // (also publishes s_item)
+        // the item after this one, resolved by thread 0 at the top of this one: its descriptor
+        // loads are in flight during the rounds
+        if (I.bin >= 0) {
+            const LdsBoxT<G> box{Fs};
+            for (int base = I.start; base < I.end; base += SST) {
+                // pushed: advanced (deposits its current); act: still in the band (appended)
+                bool act = base + tid < I.end, pushed = false;
+                PState q;
+                float X0[3] = {0.0f, 0.0f, 0.0f}, X1[3] = {0.0f, 0.0f, 0.0f}, fq = 0.0f;
+                int li = 0, lj = 0, lk = 0;
+                if (act) {
+                    unpack_raw(P, nx, q);
+                    li = q.i - I.t0x;
+                    lj = q.j - I.t0y;
+                    lk = q.l - I.t0z;
+                    const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
+                                        q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
+                                        q.o[2] >= 0.0f && q.o[2] < 1.0f;
+                    if (!inside) {
+                        // cannot happen: every binned particle was appended to the bin of its cell
+                        atomicOr(flags, DFLAG_BIN_LOST);
                         act = false;
                     } else {
-                        fq = q.w * P.idt32;
-                        if (!fixed_ok(fq, P.fscale)) {
-                            atomicOr(flags, DFLAG_FIXED_OVERFLOW);
-                            fq = 0.0f;
+                        float EB[6];
+                        gather6(box, q.o, li, lj, lk, EB);
+                        if (!advance(P, EB, P.und_kind != 0, tabA[lk + 1], tabC[lk + 1], tabS[lk + 1], q, X1)) {
+                            atomicOr(flags, DFLAG_NONFINITE);
+                            act = false;
+                        } else {
+                            fq = q.w * P.idt32;
+                            if (!fixed_ok(fq, P.fscale)) {
+                                atomicOr(flags, DFLAG_FIXED_OVERFLOW);
+                                fq = 0.0f;
+                            }
+                            for (int d = 0; d < 3; ++d) {
+                                X0[d] = q.o[d];
+                                q.o[d] = X1[d];
+                            }
+                            pushed = true;
+                            act = renormalise(P, S, q);
                         }
-                        for (int d = 0; d < 3; ++d) {
-                            X0[d] = q.o[d];
-                            q.o[d] = X1[d];
-                        }
-                        pushed = true;
-                        act = renormalise(P, S, q);
                     }
                 }
+                // destination slot: the reservation's atomic is in flight during the deposit,
+                // and so are the loads of the next round's particles
+                const int bin = act ? bin_of(P, q.i, q.j, q.l) : 0;
+                const SlotTicket tk = reserve_issue(act, bin, IO.out.cnt);
+                const int64_t ob0 = gbl(IO.out.off)[bin], ocap = gbl(IO.out.off)[bin + 1] - ob0;
+                {  // every lane loads (a clamped index past the item's end), so the waits stay static
+                    const int nb = min(base + SST + tid, I.end - 1);
+                    load_raw(IO.in, I.b0 + nb, nx, REC ? iop.id[I.sp].in : nullptr);
+                }
+                if (pushed) {
+                    Esk e;
+                    esk_setup(X0, X1, e);
+                    // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2;
+                    // one base index per component, the node offsets are immediates
+                    const int bx = li + e.base[0] + 2, by = lj + e.base[1] + 2, bz = lk + e.base[2] + 2;
+                    const int jb[3] = {bx + G::XX * (by + G::XY * bz), G::NJX + bx + G::YX * (by + G::YY * bz),
+                                       G::NJX + G::NJY + bx + G::ZX * (by + G::ZY * bz)};
+                    esk_visit<DEP>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
+                        int off;
+                        if (c == 0)  // (m, a, b) along (x, y, z)
+                            off = m + G::XX * (a + G::XY * b);
+                        else if (c == 1)  // (y, z, x)
+                            off = b + G::YX * (m + G::YY * a);
+                        else  // (z, x, y)
+                            off = a + G::ZX * (b + G::ZY * m);
+                        atomicAdd((unsigned long long *)&Js[jb[c] + off], (unsigned long long)iv);
+                    });
+                }
+                store_at(IO.out, act, reserve_slot_of(act, tk), ob0, ocap, act ? pack_cell(P, q.i, q.j, q.l) : 0,
+                         q.o, q.u, q.w, flags, REC ? iop.id[I.sp].out : nullptr, q.id);
             }
-            // destination slot: the reservation's atomic is in flight during the deposit
-            const int bin = act ? bin_of(P, q.i, q.j, q.l) : 0;
-            const SlotTicket tk = reserve_issue(act, bin, IO.out.cnt);
-            if (pushed) {
-                Esk e;
-                esk_setup(X0, X1, e);
-                // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2;
-                // one base index per component, the node offsets are immediates
-                const int bx = li + e.base[0] + 2, by = lj + e.base[1] + 2, bz = lk + e.base[2] + 2;
-                const int jb[3] = {bx + G::XX * (by + G::XY * bz), G::NJX + bx + G::YX * (by + G::YY * bz),
-                                   G::NJX + G::NJY + bx + G::ZX * (by + G::ZY * bz)};
-                esk_visit<DEP>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
-                    int off;
-                    if (c == 0)  // (m, a, b) along (x, y, z)
-                        off = m + G::XX * (a + G::XY * b);
-                    else if (c == 1)  // (y, z, x)
-                        off = b + G::YX * (m + G::YY * a);
-                    else  // (z, x, y)
-                        off = a + G::ZX * (b + G::ZY * m);
-                    atomicAdd((unsigned long long *)&Js[jb[c] + off], (unsigned long long)iv);
-                });
-            }
-            store_in_bin(IO.out, act, reserve_slot_of(act, tk), bin, act ? pack_cell(P, q.i, q.j, q.l) : 0, q.o, q.u,
-                         q.w, flags, REC ? iop.id[sp].out : nullptr, q.id);
         }
-        __syncthreads();
-        // flush nonzero LDS currents with global 64-bit integer atomics
-        for (int k = tid; k < G::NJ; k += SST) {
-            const long long v = Js[k];
-            if (v == 0) continue;
-            int kk = k, x, y, z;
-            long long *J;
-            if (kk < G::NJX) {
-                const int yz = kk / G::XX;
-                x = kk - yz * G::XX;
-                z = yz / G::XY;
-                y = yz - z * G::XY;
-                J = Jx;
-            } else if (kk < G::NJX + G::NJY) {
-                kk -= G::NJX;
-                const int yz = kk / G::YX;
-                x = kk - yz * G::YX;
-                z = yz / G::YY;
-                y = yz - z * G::YY;
-                J = Jy;
-            } else {
-                kk -= G::NJX + G::NJY;
-                const int yz = kk / G::ZX;
-                x = kk - yz * G::ZX;
-                z = yz / G::ZY;
-                y = yz - z * G::ZY;
-                J = Jz;
-            }
-            const int l = t0z - 2 + z;
-            if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
-            const int64_t o = near_cell<TY == 1>(P, t0x - 2 + x, t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
-            atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
+        if (tid == 0) {
+            claim = atomicAdd(&qnext[q * QPAD], 1);
+            s_item = resolve();
         }
+        // every deposit of this item is in the current boxes
         __syncthreads();
+        const int next = __builtin_amdgcn_readfirstlane(s_item);
+        ItemT N{};
+        if (next >= 0) N = decode(next);
+        const ItemT C = I;
+        // the next item's fields and first particles are on their way during this item's flush
+        if (next >= 0) {
+            I = N;
+            if (I.bin >= 0) {
+                stage(I);
+                if (I.start + tid < I.end)
+                    load_raw(iop.s[I.sp].in, I.b0 + I.start + tid, nx, REC ? iop.id[I.sp].in : nullptr);
+            }
+        }
+        // flush nonzero LDS currents with global 64-bit integer atomics, clearing the boxes
+        if (C.bin >= 0)
+            for (int k = tid; k < G::NJ; k += SST) {
+                const long long v = Js[k];
+                if (v == 0) continue;
+                Js[k] = 0;
+                int kk = k, x, y, z;
+                long long *J;
+                if (kk < G::NJX) {
+                    const int yz = kk / G::XX;
+                    x = kk - yz * G::XX;
+                    z = yz / G::XY;
+                    y = yz - z * G::XY;
+                    J = Jx;
+                } else if (kk < G::NJX + G::NJY) {
+                    kk -= G::NJX;
+                    const int yz = kk / G::YX;
+                    x = kk - yz * G::YX;
+                    z = yz / G::YY;
+                    y = yz - z * G::YY;
+                    J = Jy;
+                } else {
+                    kk -= G::NJX + G::NJY;
+                    const int yz = kk / G::ZX;
+                    x = kk - yz * G::ZX;
+                    z = yz / G::ZY;
+                    y = yz - z * G::ZY;
+                    J = Jz;
+                }
+                const int l = C.t0z - 2 + z;
+                if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
+                const int64_t o = near_cell<TY == 1>(P, C.t0x - 2 + x, C.t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
+                atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
+            }
+        cur = next;
     }
 }
 
@@ -1435,6 +1600,7 @@ void split_step(Ctx &c, const StepCtx &S) {
     timing_end(c, 0, t2);
     hipEvent_t t3 = timing_begin(c);
     if (P.ions) launch_ion_fixed(P, c.sh_lo, c.sh_hi - c.sh_lo, S.t, S.t1, S.k0, c.jioni, c.dflags, c.st);
+    launch_neutraliser_current(c, S);
     timing_end(c, 2, t3);
     hipEvent_t t4 = timing_begin(c);
     launch_bhalf<float>(P, S.k0r, f, (float)P.dt, (float *)c.murbuf, c.st);  // B^(n-1/2) -> B^(n+1/2)
