@@ -151,6 +151,15 @@ typedef struct {
  * wg_per_cu: resident workgroups per compute unit of the FP32 particle kernel's
  *            persistent grid; 0 = as many as registers and LDS allow.
  * init_fields: 0 = E = B = 0 at t' = 0 (a frozen neutralising background);
+ *              2 = E = B = 0 at t' = 0 with the neutralising charge made explicit
+ *              and faded out (section 3's artificial ions): a charge equal and
+ *              opposite to the beam's at t' = 0, at rest, that falls linearly to
+ *              zero over neutral_fade_s seconds (boosted frame); the current that
+ *              removes it is -E_b d/dt(fraction left), E_b the charge's
+ *              electrostatic field (the problem below with gamma_b = 1), so the
+ *              charge leaves as continuity demands and Gauss's law keeps its
+ *              residual; the Gauss diagnostic counts the charge.  Transverse
+ *              grid edges up to 2048;
  *              1 = the beam's self-field: its rest-frame electrostatic field
  *              carried into the boosted frame (section 1 field
  *              transformation), i.e. (d_xx + d_yy + d_zz / gamma_b^2) phi =
@@ -158,7 +167,8 @@ typedef struct {
  *              the z faces; gamma_b from the beam's mean boosted beta_z),
  *              E = -(d_x, d_y, d_z / gamma_b^2) phi, B = beta_b z x E at
  *              t' = -dt/2.  Transverse grid edges up to 2048.
- * stream: hipStream_t for all launches (NULL: null stream). */
+ * stream: hipStream_t for all launches (NULL: null stream).
+ * neutral_fade_s: the fade time of init_fields = 2 (> 0); ignored otherwise. */
 typedef struct {
     int32_t precision, pusher;
     double fp64_gamma_threshold;
@@ -167,6 +177,7 @@ typedef struct {
     int32_t record, variant;
     int32_t wg_per_cu, init_fields;
     void *stream;
+    double neutral_fade_s;
 } pic_options;
 
 typedef struct {

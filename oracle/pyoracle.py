@@ -310,12 +310,14 @@ def push(pusher: int, qm: float, dt: float, u, E, B):
 # by node.  The state between steps is (E^n, B^(n-1/2)): the pattern moves at
 # beta_b, so B is taken at t' = -dt/2, i.e. beta_b z x E displaced by
 # beta_b dt / 2 along z (linear interpolation between the planes).
-def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: float):
+def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: float, open_top: bool = False):
     """phi, (Ex, Ey, Ez), (Bx, By, Bz) for node charge rho of shape (nz, ny, nx).
 
     The transverse operator is diagonalised with a 2D FFT (library primitive);
     each (kx, ky) column is then a tridiagonal system in z, solved by plain
-    forward elimination and back substitution."""
+    forward elimination and back substitution.  phi = 0 one plane below the
+    back face, and one plane above the top face -- or, with open_top, equal
+    there to the top plane's (no field through the top face)."""
     rho = np.asarray(rho, dtype=np.float64)
     nz, ny, nx = rho.shape
     g2 = 1.0 / (gamma_b * gamma_b)
@@ -329,7 +331,7 @@ def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: flo
     cp[0] = g2 / diag
     dp[0] = -R[0] / diag
     for l in range(1, nz):
-        m = diag - g2 * cp[l - 1]
+        m = (diag + g2 if open_top and l == nz - 1 else diag) - g2 * cp[l - 1]
         cp[l] = g2 / m
         dp[l] = (-R[l] - g2 * dp[l - 1]) / m
     ph = np.empty_like(dp)
@@ -337,7 +339,8 @@ def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: flo
     for l in range(nz - 2, -1, -1):
         ph[l] = dp[l] - cp[l] * ph[l + 1]
     phi = np.real(np.fft.ifft2(ph, axes=(1, 2)))
-    up = np.concatenate([phi[1:], np.zeros((1, ny, nx))], axis=0)  # phi one plane up (0 beyond the top)
+    above = phi[-1:] if open_top else np.zeros((1, ny, nx))
+    up = np.concatenate([phi[1:], above], axis=0)  # phi one plane up
     Ex = -(np.roll(phi, -1, axis=2) - phi)
     Ey = -(np.roll(phi, -1, axis=1) - phi)
     Ez = -(up - phi) * g2
@@ -354,10 +357,18 @@ def relativistic_poisson(rho: np.ndarray, gamma_b: float, beta_b: float, dt: flo
 def init_neutraliser(sim: "Sim", fade_s: float):
     """Section 3's neutralising ions: a charge equal and opposite to the beam's at t' = 0, faded
     linearly to zero over fade_s seconds (boosted frame) while the fields start from zero; its
-    field is the beam charge's electrostatic field (the relativistic Poisson problem at rest)."""
-    rho = np.real(sim.rho(1))
-    _, E, _ = relativistic_poisson(rho, 1.0, 0.0, sim.info().dt)
-    arrs = [np.ascontiguousarray(a, dtype=sim.dtype) for a in (rho,) + tuple(E)]
+    field is the beam charge's electrostatic field (the relativistic Poisson problem at rest)
+    with no field through the top face and none on the top plane, which the front face holds
+    at zero."""
+    _, E, _ = relativistic_poisson(np.real(sim.rho(1)), 1.0, 0.0, sim.info().dt, open_top=True)
+    Ex, Ey, Ez = (e.copy() for e in E)
+    Ex[-1] = 0.0  # the front face keeps its tangential E at zero: none of the field may sit there
+    Ey[-1] = 0.0
+    # the charge is the field's divergence on the nodes (x, y periodic, E_z below plane 0 left
+    # out, as the oracle's Gauss residual does): the beam's, except on the top plane
+    rho = (Ex - np.roll(Ex, 1, axis=2)) + (Ey - np.roll(Ey, 1, axis=1)) + Ez
+    rho[1:] -= Ez[:-1]
+    arrs = [np.ascontiguousarray(a, dtype=sim.dtype) for a in (rho, Ex, Ey, Ez)]
     sim.L.orc_set_fading_charge(sim.h, *[a.ctypes.data for a in arrs], float(fade_s))
     return arrs
 

@@ -52,7 +52,8 @@ class pic_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pusher", C.c_int32), ("fp64_gamma_threshold", C.c_double),
                 ("fixed_point_frac_bits", C.c_int32), ("check_every", C.c_int32), ("tile", C.c_int32 * 3),
                 ("max_steps", C.c_int32), ("record", C.c_int32), ("variant", C.c_int32),
-                ("wg_per_cu", C.c_int32), ("init_fields", C.c_int32), ("stream", C.c_void_p)]
+                ("wg_per_cu", C.c_int32), ("init_fields", C.c_int32), ("stream", C.c_void_p),
+                ("neutral_fade_s", C.c_double)]
 
 
 class pic_layout(C.Structure):
@@ -141,7 +142,7 @@ class PicError(RuntimeError):
 
 def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHER_AUTO, record=0, max_steps=0,
                           check_every=0, tile=(0, 0, 0), frac_bits=0, gamma_threshold=0.0, stream=None,
-                          normals=None, variant=0, wg_per_cu=0, init_fields=0):
+                          normals=None, variant=0, wg_per_cu=0, init_fields=0, neutral_fade_s=0.0):
     """Fill the C structs from a workload dictionary (plain field copies)."""
     g, fr, b, p, u = w["grid"], w["frame"], w["beam"], w["plasma"], w["undulator"]
     grid = pic_grid(g["nx"], g["ny"], g["nz"], 0, g["dx_m"], g["cfl"])
@@ -177,4 +178,5 @@ def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHE
     opt.wg_per_cu = wg_per_cu
     opt.init_fields = init_fields
     opt.stream = stream
+    opt.neutral_fade_s = neutral_fade_s
     return grid, frame, beam, plasma, und, opt

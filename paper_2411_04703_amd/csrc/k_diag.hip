@@ -385,6 +385,7 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
         if (P.ions && c.sh_hi > c.sh_lo)
             hipLaunchKernelGGL(k_rho_ion, dim3(nblocks(c.sh_hi - c.sh_lo, 128)), dim3(128), 0, c.st, P, c.sh_lo,
                                c.sh_hi - c.sh_lo, o->t, c.k0, ion);
+        launch_neutraliser_rho(c, rho);
         int nblk = nblocks(P.nc, DT);
         int64_t dk = c.k0 - c.rprev_k0;
         if (c.precision == PIC_FP64_PLAIN) {

@@ -75,7 +75,9 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (o->pusher < -1 || o->pusher > 1) return fail(err, PIC_EINVAL, "options: pusher");
     if (o->variant < 0 || o->variant > 2) return fail(err, PIC_EINVAL, "options: variant 0, 1 or 2");
     if (o->wg_per_cu < 0 || o->wg_per_cu > 8) return fail(err, PIC_EINVAL, "options: wg_per_cu in [0, 8]");
-    if (o->init_fields != 0 && o->init_fields != 1) return fail(err, PIC_EINVAL, "options: init_fields is 0 or 1");
+    if (o->init_fields < 0 || o->init_fields > 2) return fail(err, PIC_EINVAL, "options: init_fields is 0, 1 or 2");
+    if (o->init_fields == 2 && !(o->neutral_fade_s > 0.0 && std::isfinite(o->neutral_fade_s)))
+        return fail(err, PIC_EINVAL, "options: init_fields = 2 needs neutral_fade_s > 0");
     if (o->init_fields && (g->nx > 2048 || g->ny > 2048))
         return fail(err, PIC_EINVAL, "options: init_fields needs transverse grid edges <= 2048");
 
@@ -274,6 +276,10 @@ static pic_status make_plan(const pic_grid *g, const pic_frame *f, const pic_bea
     off[18] = take(8 * 6 * (uint64_t)std::max<int64_t>(b->n_macro, 1));  // normals staging
     off[19] = take(256);                                            // device flags + lab-probe sums
     off[22] = take(8 * 2 * (uint64_t)(nblocks(nmax, 256) + 4));     // scan scratch
+    if (o->init_fields == 2) {
+        off[25] = take(8 * 3 * (uint64_t)P.nc);  // neutralising charge: its field
+        off[26] = take(8 * (uint64_t)P.nc);      // and its node charge
+    }
     pl.arena = a;
     // state: header + E, B + particles
     uint64_t fb = o->precision == PIC_FP64_PLAIN ? 8 : 4;
@@ -412,6 +418,7 @@ static pic_status step64(Ctx &c) {
     timing_end(c, 0, t1);
     hipEvent_t t2 = timing_begin(c);
     if (P.ions) launch_ion64(P, c.sh_lo, c.sh_hi - c.sh_lo, S.t, S.t1, S.k0, c.jion64, c.st);
+    launch_neutraliser_current(c, S);
     timing_end(c, 2, t2);
     hipEvent_t t3 = timing_begin(c);
     launch_bhalf<double>(P, S.k0r, f, 0.5 * P.dt, (double *)c.murbuf, c.st);
@@ -516,6 +523,10 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
     c->probe_acc = (double *)(A + off[19] + 64);  // same 256-byte block: flags, then the probe's sums
     c->i64scratch = (int64_t *)(A + off[22]);
     c->murbuf = A + off[10];
+    if (o->init_fields == 2) {
+        for (int k = 0; k < 3; ++k) c->fc_E[k] = (double *)(A + off[25]) + k * P.nc;
+        c->fc_rho = (double *)(A + off[26]);
+    }
     hipError_t e = hipMemsetAsync(c->dflags, 0, 256, c->st);
     if (e == hipSuccess) e = hipMemsetAsync(A + off[9], 0, 8 * P.nz, c->st);
     if (pl.precision == PIC_FP64_PLAIN) {
@@ -603,7 +614,11 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
     } else {
         s = split_plasma_fill(*c);
     }
-    if (s == PIC_OK && o->init_fields && b->n_macro > 0) s = init_beam_fields(*c);
+    if (s == PIC_OK && o->init_fields == 1 && b->n_macro > 0) s = init_beam_fields(*c);
+    if (s == PIC_OK && o->init_fields == 2 && b->n_macro > 0) {
+        c->fc_T = o->neutral_fade_s * kC / g->dx_m;
+        s = init_neutraliser(*c);
+    }
     if (s != PIC_OK) {
         fprintf(stderr, "pic_init: %s\n", c->err.c_str());
         if (c->split) split_free(*c);

@@ -44,6 +44,10 @@ struct Ctx {
     double bw = 0, k_bunch_default = 0;
     // window position (cells) at time t: win_x0 + bw (t - win_t0); k0 = its floor, at most one shift per step
     double win_x0 = 0, win_t0 = 0;
+    // neutralising charge faded over fc_T (normalised time; 0 = none): its node charge and
+    // electrostatic field at t' = 0 (FP64, planes of the window at origin 0)
+    double fc_T = 0;
+    double *fc_rho = nullptr, *fc_E[3] = {};
     double beam_beta0 = 0;  // mean boosted beta_z of the beam at t' = 0
     int probe_on = 0;       // lab-frame probe armed
     double probe_t = 0, probe_k = 0;
@@ -142,8 +146,12 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *out);
 void beam_rho(Ctx &c, double *rho);  // beam charge on the nodes (ring order), added into rho
 void probe_step(Ctx &c);             // lab-frame probe: sample the beam particles that crossed its lab time
 
-// initial beam self-field (k_initfield.hip)
+// initial beam self-field and the faded neutralising charge (k_initfield.hip)
 pic_status init_beam_fields(Ctx &c);
+pic_status init_neutraliser(Ctx &c);
+double neutraliser_left(const Ctx &c, double t);  // fraction of the neutralising charge left at time t
+void launch_neutraliser_current(Ctx &c, const StepCtx &S);  // adds its current of the step into J
+void launch_neutraliser_rho(Ctx &c, double *rho);           // adds its charge now into rho (ring order)
 
 // adjoint (k_adjoint.hip)
 pic_status adjoint_seed(Ctx &c, double kb, double *lam, double *loss);

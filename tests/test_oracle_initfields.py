@@ -170,3 +170,74 @@ def test_initial_b_time_level_converges_at_third_order():
     for wrong in (0, -1):
         assert 3.9 < res[wrong][0] / res[wrong][1] < 4.1, res
         assert res[wrong][1] > 30 * res[1][1], res
+
+
+def _fade_case():
+    w = _beam_only(nx=32, ny=32, nz=64, n=16384, sigma=(3, 3, 6))
+    return w, pin.beam_normals(w["beam"]["n_macro"], 1)
+
+
+FADE_CELLS = 10.0  # fade time in cells / c
+
+
+def _fade_seconds(w):
+    return FADE_CELLS * w["grid"]["dx_m"] / 299792458.0
+
+
+def test_neutraliser_fades_with_gauss_law_kept():
+    """Section 3's artificial ions: a charge opposite to the beam's at t' = 0, faded linearly to
+    zero over T and carried off by the current -E_b f'(t) (E_b its electrostatic field, the
+    charge E_b's divergence).  div E - rho keeps its value at t' = 0 on every interior node, to
+    round-off, through the fade and after it, as the window moves (the residual is compared plane
+    by plane in the boosted frame).  That value is zero except on the window's top plane at
+    t' = 0, where E_b leaves out the components the front face holds at zero: 5e-3 of the peak
+    charge at most.  Leaving the faded charge out of rho shows what was carried: the residual
+    then differs by f(t) times the charge."""
+    w, nrm = _fade_case()
+    s = po.Sim(w, nrm)
+    arrs = po.init_neutraliser(s, _fade_seconds(w))
+    rho_n = arrs[0].reshape(s.rho(1).shape)
+    nz = rho_n.shape[0]
+    scale = np.abs(np.real(s.rho(1))).max()
+    r0 = np.real(s.gauss())  # (plane 0: the back face, which the divergence sees only in part)
+    assert np.abs(r0[1:-1]).max() <= 1e-12 * scale and 0 < np.abs(r0[-1]).max() <= 5e-3 * scale
+    dt = s.info().dt
+    seen = []
+    for n in range(0, 40, 4):
+        t = s.info().step * dt
+        k0 = s.info().k0
+        r = np.real(s.gauss())
+        # plane l of the window is plane k0 + l of the window at t' = 0
+        drift = r[8:nz - 8 - k0] - r0[8 + k0:nz - 8] if k0 < nz - 16 else np.zeros(1)
+        assert np.abs(drift).max() <= 1e-12 * scale, (n, np.abs(drift).max() / scale)
+        f = max(0.0, 1.0 - t / FADE_CELLS)
+        carried = np.real(s.rho(8))  # the faded charge's part of rho now
+        expect = np.zeros_like(rho_n)
+        expect[: nz - k0] = -f * rho_n[k0:]
+        assert np.abs(carried - expect).max() <= 1e-14 * scale, n
+        seen.append((f, k0))
+        s.step(4)
+    assert seen[-1][0] == 0.0 and seen[-1][1] > 0 and 0.0 < seen[2][0] < 1.0
+
+
+def test_neutraliser_field_nears_the_beams_own():
+    """After the fade the beam carries (close to) its self-consistent field -- the moving beam's
+    relativistic field -- where from a frozen neutralising background it starts without one and
+    is still far from it: transverse E within 25 % of it after the fade against 80 % off."""
+    w = _beam_only(nx=32, ny=32, nz=96, n=32768, sigma=(3, 3, 6))
+    w["beam"]["charge_C"] = 3e-12
+    w["beam"]["rel_energy_spread_rms"] = 0.0
+    w["beam"]["emit_n_m"] = [1e-9, 1e-9]
+    nrm = pin.beam_normals(w["beam"]["n_macro"], 1)
+    off = []
+    for fade in (False, True):
+        s = po.Sim(w, nrm)
+        if fade:
+            po.init_neutraliser(s, _fade_seconds(w))
+        s.step(int((FADE_CELLS + 20.0) / s.info().dt))
+        beta = po.beam_mean_beta(s)
+        gamma = 1.0 / math.sqrt((1.0 - beta) * (1.0 + beta))
+        _, E, _ = po.relativistic_poisson(np.real(s.rho(1)), gamma, beta, s.info().dt)
+        sc = max(np.abs(e[8:-8]).max() for e in E[:2])
+        off.append(max(np.abs(s.field(f)[8:-8] - e[8:-8]).max() / sc for f, e in zip(("Ex", "Ey"), E[:2])))
+    assert off[0] > 0.8 and off[1] < 0.25, off
