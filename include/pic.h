@@ -208,12 +208,25 @@ PIC_API pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_bea
                     const pic_undulator *u, const pic_options *o, void *arena, uint64_t arena_bytes,
                     pic_ctx **out);
 
-/* Advance nsteps steps (gather, push, deposit, ion current, FDTD, window,
- * injection).  Asynchronous on the context stream. */
+/* Advance nsteps steps of the boosted-frame PIC loop of section 1: field
+ * gather at the particles, leap-frog push (after Eq. Vprime; Boris or Vay),
+ * charge-conserving current deposit (Eq. Max3 by current weighting), the
+ * immobile ions' current v_R rho_i (after Eq. Max4), the Yee update of the
+ * curl equations (Eq. Max1, Max2), then the window shift and plasma
+ * injection of a window co-moving with the beam (section 3).  nsteps >= 0
+ * (PIC_EINVAL otherwise).  Errors found at the flag checks (every
+ * check_every steps in FP32 mode): PIC_ERANGE for a fixed-point current
+ * overflow or a plasma count past the capacity, PIC_ESTATE for a non-finite
+ * momentum, PIC_ENOMEM when full bins lost particles; the state is then not
+ * to be continued (restore a snapshot).  Asynchronous on the context stream. */
 PIC_API pic_status pic_step(pic_ctx *c, int32_t nsteps);
 
 /* Diagnostics (synchronising).  mask: PIC_DIAG_MOMENTS | PIC_DIAG_BUNCHING |
- * PIC_DIAG_ENERGY | PIC_DIAG_GAUSS.  Bunching b(k) = |sum_beam w exp(i k z')| /
+ * PIC_DIAG_ENERGY | PIC_DIAG_GAUSS.  The quantities sections 3 and 4 follow:
+ * beam sizes, momenta and emittances (moments), the density modulation the
+ * beam picks up (bunching) and the energy bookkeeping; the Gauss residual
+ * checks Eq. Max3's constraint div E = rho, which the charge-conserving
+ * deposit keeps.  Bunching b(k) = |sum_beam w exp(i k z')| /
  * sum w at k = 2 pi / bunch_period_cells and 2k (boosted frame, fixed t').
  * Gauss: r = div E - rho on nodes at least 8 planes from the z faces; reports
  * max |r| and max |r - r_prev| against the previous Gauss call (planes aligned
@@ -241,7 +254,13 @@ enum {
     PIC_A_BEAM = 16,   /* double [7][n]: x y z ux uy uz w  (n = slots) */
     PIC_A_BEAM_ALIVE,  /* int32 [n] */
     PIC_A_PLASMA,      /* double [7][n] */
-    PIC_A_PLASMA_ALIVE /* int32 [n] */
+    PIC_A_PLASMA_ALIVE, /* int32 [n] */
+    /* the beam in the lab frame at the current boosted time t' (section 2, the inverse of
+     * Eq. Lor1, Lor2; each particle at its own lab time): double [8][n], rows x, y, z_lab,
+     * t_lab, ux, uy, uz_lab, gamma_lab, with t_lab = gR (t' + bR (z' - z0)),
+     * z_lab = gR (z' - z0 + bR t'), uz_lab = gR (uz' + bR gamma'), gamma_lab = gR (gamma' + bR uz'),
+     * z0 = pic_derived.z_offset_cells; slots and alive flags as PIC_A_BEAM */
+    PIC_A_BEAM_LAB
 };
 PIC_API pic_status pic_read(pic_ctx *c, int32_t which, void *dst, int64_t *count);
 
@@ -275,7 +294,27 @@ PIC_API pic_status pic_state_to_fp64(const pic_ctx *src, pic_ctx *dst);
 PIC_API pic_status pic_lab_probe(pic_ctx *c, double t_lab, double k_lab);
 PIC_API pic_status pic_lab_probe_read(pic_ctx *c, double out[5]);
 
-/* Checkpoint: copy the full dynamic state (particles, fields, window origin,
+/* Lab-frame groups of the beam (section 2): at one boosted instant t' the beam's
+ * particles sit at lab times spread over gR bR dz' for a slice dz' along z (Eq. DT),
+ * and particles of unequal u'_z move their lab times on unequally; grouping them by
+ * slices of z' (absolute boosted cells, as pic_read returns them) and of u'_z keeps
+ * each group's lab-time span small.  Group (iz, iu), iz = floor((z' - z_lo) / dz) in
+ * [0, nz), iu = floor((u'_z - u_lo) / du) in [0, nu), is entry iz nu + iu of dst
+ * (DEVICE, nz nu x 16 doubles): count, sum w, sum w t_lab, min t_lab, max t_lab,
+ * sum w z_lab, sum w z_lab^2, sum w x, sum w x^2, sum w y, sum w y^2, sum w ux,
+ * sum w ux^2, sum w uy, sum w uy^2, sum w gamma_lab (lab quantities as
+ * PIC_A_BEAM_LAB); particles outside every group are left out.  At most 256 groups
+ * (PIC_EINVAL otherwise).  Synchronising; FP64 sums in an order that depends on the
+ * particles' (rounding at 1e-16). */
+typedef struct {
+    double z_lo, dz, u_lo, du;
+    int32_t nz, nu;
+} pic_lab_groups_spec;
+enum { PIC_LAB_GROUP_VALUES = 16 };
+PIC_API pic_status pic_lab_groups(pic_ctx *c, const pic_lab_groups_spec *spec, void *dst);
+
+/* Checkpoint (the paper describes none; the step of section 1 depends on
+ * nothing outside this state): copy the full dynamic state (particles, fields, window origin,
  * step counter, injection cursors; FP32 mode also its bin layout) into / out
  * of a DEVICE buffer of layout.state_bytes, between steps.  A snapshot
  * restores into any context of the same configuration and continues
@@ -284,7 +323,12 @@ PIC_API pic_status pic_lab_probe_read(pic_ctx *c, double out[5]);
 PIC_API pic_status pic_get_state(pic_ctx *c, void *dst);
 PIC_API pic_status pic_set_state(pic_ctx *c, const void *src);
 
-/* Adjoint (FP64 mode with record = 1).  The adjoint vector has the layout of
+/* Adjoint (FP64 mode with record = 1; the paper gives none): the exact
+ * reverse-mode derivative of one step of pic_step's discrete scheme (section 1:
+ * gather, push, deposit, ion current, Yee update; window shift and injection
+ * as index maps), for gradients of the bunching factor of sections 3 and 4
+ * with respect to the undulator parameter K (Eq. M1-M4's field amplitude)
+ * and the plasma density n0 (Eq. Nnormi).  The adjoint vector has the layout of
  * the forward state: [beam x,y,z,ux,uy,uz (beam slots each)] [plasma 6 x plasma
  * slots] [E 3 x cells] [B 3 x cells], doubles on the DEVICE, particle blocks
  * sized by pic_lambda_len().  pic_adjoint_seed_bunching() writes dL/dstate of

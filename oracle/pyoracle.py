@@ -392,6 +392,57 @@ def init_beam_fields(sim: "Sim"):
 
 
 # ---------------------------------------------------------------------------
+# The beam in the lab frame at one boosted instant (section 2; the inverse
+# Lorentz transform of each particle's event and four-velocity, Eq. Lor1 and
+# Lor2 read backwards): lab time gR (t' + bR (z' - z0)), lab position
+# gR (z' - z0 + bR t'), transverse coordinates unchanged,
+# u_z,lab = gR (u'_z + bR gamma'), gamma_lab = gR (gamma' + bR u'_z).
+def lab_beam(sim: "Sim") -> dict:
+    """Per beam slot: x, y, z_lab, t_lab, ux, uy, uz_lab, gamma_lab, alive."""
+    i = sim.info()
+    gR, bR, zc = i.gR, i.bR, i.zoff
+    t = i.step * i.dt
+    p = sim.particles(0)
+    x, y, z, ux, uy, uz = (np.real(p[k]) for k in ("x", "y", "z", "ux", "uy", "uz"))
+    g = np.sqrt(1.0 + ux * ux + uy * uy + uz * uz)
+    return {"x": x, "y": y, "z": gR * (z - zc + bR * t), "t": gR * (t + bR * (z - zc)), "ux": ux, "uy": uy,
+            "uz": gR * (uz + bR * g), "gamma": gR * (g + bR * uz), "alive": p["alive"],
+            "w": np.real(p["w"]), "z_boost": z, "uz_boost": uz}
+
+
+# Groups of the beam by slices of boosted z' and u'_z (section 2, Eq. DT: a
+# slice dz' of the beam at one boosted instant spans lab times gR bR dz').
+LAB_GROUP_FIELDS = ("count", "w", "w_t", "t_min", "t_max", "w_z", "w_zz", "w_x", "w_xx", "w_y", "w_yy", "w_ux",
+                    "w_uxux", "w_uy", "w_uyuy", "w_gamma")
+
+
+def lab_groups(sim: "Sim", z_lo: float, dz: float, nz: int, u_lo: float = -1e300, du: float = 1e308,
+               nu: int = 1) -> np.ndarray:
+    """(nz * nu, 16) table, group iz * nu + iu holding the live beam particles with
+    floor((z' - z_lo) / dz) = iz and floor((u'_z - u_lo) / du) = iu; columns
+    LAB_GROUP_FIELDS (min/max +inf/-inf for an empty group)."""
+    L = lab_beam(sim)
+    iz = np.floor((L["z_boost"] - z_lo) / dz)
+    iu = np.floor((L["uz_boost"] - u_lo) / du)
+    out = np.zeros((nz * nu, 16))
+    out[:, 3], out[:, 4] = np.inf, -np.inf
+    for a in range(nz):
+        for b in range(nu):
+            m = (L["alive"] == 1) & (iz == a) & (iu == b)
+            w = L["w"][m]
+            row = out[a * nu + b]
+            row[0] = m.sum()
+            row[1] = w.sum()
+            row[2] = (w * L["t"][m]).sum()
+            if m.any():
+                row[3], row[4] = L["t"][m].min(), L["t"][m].max()
+            for c, k in zip((5, 7, 9, 11, 13), ("z", "x", "y", "ux", "uy")):
+                row[c] = (w * L[k][m]).sum()
+                row[c + 1] = (w * L[k][m] ** 2).sum()
+            row[15] = (w * L["gamma"][m]).sum()
+    return out
+
+
 # Lab-frame probe (section 2: relating the boosted frame's data to the lab).
 # A particle at boosted position z' and time t' is at lab time
 # t = gR (t' + bR (z' - z0)) and lab position z_lab = gR (z' - z0 + bR t'),

@@ -17,7 +17,8 @@ PIC_FP64_PLAIN, PIC_FP32_SPLIT = 0, 1
 PIC_BORIS, PIC_VAY, PIC_PUSHER_AUTO = 0, 1, -1
 PIC_DIAG_MOMENTS, PIC_DIAG_BUNCHING, PIC_DIAG_ENERGY, PIC_DIAG_GAUSS = 1, 2, 4, 8
 PIC_A_EX, PIC_A_EY, PIC_A_EZ, PIC_A_BX, PIC_A_BY, PIC_A_BZ = range(6)
-PIC_A_BEAM, PIC_A_BEAM_ALIVE, PIC_A_PLASMA, PIC_A_PLASMA_ALIVE = 16, 17, 18, 19
+PIC_A_BEAM, PIC_A_BEAM_ALIVE, PIC_A_PLASMA, PIC_A_PLASMA_ALIVE, PIC_A_BEAM_LAB = 16, 17, 18, 19, 20
+PIC_LAB_GROUP_VALUES = 16
 
 STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVICE", -4: "PIC_ESTATE", -5: "PIC_ERANGE"}
 
@@ -56,6 +57,11 @@ class pic_options(C.Structure):
                 ("neutral_fade_s", C.c_double)]
 
 
+class pic_lab_groups_spec(C.Structure):
+    _fields_ = [("z_lo", C.c_double), ("dz", C.c_double), ("u_lo", C.c_double), ("du", C.c_double),
+                ("nz", C.c_int32), ("nu", C.c_int32)]
+
+
 class pic_layout(C.Structure):
     _fields_ = [("arena_bytes", C.c_uint64), ("state_bytes", C.c_uint64), ("beam_capacity", C.c_int64),
                 ("plasma_capacity", C.c_int64)]
@@ -87,7 +93,7 @@ class pic_diag_out(C.Structure):
 EXPORTS = ("pic_query_layout", "pic_derive", "pic_init", "pic_step", "pic_diag", "pic_read", "pic_write",
            "pic_get_state", "pic_set_state", "pic_lambda_len", "pic_adjoint_seed_bunching", "pic_adjoint_step",
            "pic_timing", "pic_timing_read", "pic_sync", "pic_free", "pic_last_error", "pic_state_to_fp64",
-           "pic_lab_probe", "pic_lab_probe_read", "pic_set_window_beta")
+           "pic_lab_probe", "pic_lab_probe_read", "pic_set_window_beta", "pic_lab_groups")
 
 _lib = None
 
@@ -122,6 +128,7 @@ def load() -> C.CDLL:
     L.pic_timing.argtypes = [C.c_void_p, C.c_int32]
     L.pic_timing_read.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
     L.pic_set_window_beta.argtypes = [C.c_void_p, C.c_double]
+    L.pic_lab_groups.argtypes = [C.c_void_p, P(pic_lab_groups_spec), C.c_void_p]
     L.pic_sync.argtypes = [C.c_void_p]
     L.pic_free.argtypes = [C.c_void_p]
     L.pic_last_error.argtypes = [C.c_void_p]

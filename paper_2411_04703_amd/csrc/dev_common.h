@@ -63,6 +63,86 @@ __device__ inline void probe_particle(const Params &P, double z1, double ux, dou
     v[4] += w * zl * zl;
 }
 
+// Lab-frame phase space of a particle at boosted time t (section 2, the inverse
+// of Eq. Lor1, Lor2): lab time gR (t + bR (z - zoff)), lab position
+// gR (z - zoff + bR t), u_z,lab = gR (u_z + bR gamma), gamma_lab = gR (gamma + bR u_z);
+// x, y, u_x, u_y are frame invariant.  Out: x y z_lab t_lab ux uy uz_lab gamma_lab.
+__device__ inline void lab_of(const Params &P, double t, double x, double y, double z, double ux, double uy, double uz,
+                              double out[8]) {
+    const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz), zr = z - P.zoff;
+    out[0] = x;
+    out[1] = y;
+    out[2] = P.gR * (zr + P.bR * t);
+    out[3] = P.gR * (t + P.bR * zr);
+    out[4] = ux;
+    out[5] = uy;
+    out[6] = P.gR * (uz + P.bR * g);
+    out[7] = P.gR * (g + P.bR * uz);
+}
+
+// Grouping of the beam (section 2: at one boosted instant a beam spans a lab
+// time gR bR dz' over a slice dz' along the propagation direction, Eq. DT, and
+// particles of unequal u'_z advance their lab time unequally): group of a
+// particle by its boosted z' and u'_z slices; per group 16 values:
+// count, sum w, sum w t_lab, min t_lab, max t_lab, sum w z_lab, sum w z_lab^2,
+// sum w x, sum w x^2, sum w y, sum w y^2, sum w ux, sum w ux^2, sum w uy,
+// sum w uy^2, sum w gamma_lab.
+enum { LAB_GROUP_VALUES = 16, LAB_GROUPS_MAX = 256 };
+struct LabGroupSpec {
+    double z_lo, dz, u_lo, du;
+    int nz, nu;
+};
+__device__ inline int lab_group_of(const LabGroupSpec &G, double z, double uz) {
+    const double fz = floor((z - G.z_lo) / G.dz), fu = floor((uz - G.u_lo) / G.du);
+    if (!(fz >= 0.0 && fz < G.nz && fu >= 0.0 && fu < G.nu)) return -1;
+    return (int)fz * G.nu + (int)fu;
+}
+
+// a block's LDS table of groups (cleared by the block: counts and sums 0, min +inf, max -inf)
+__device__ inline void lab_table_clear(double *tab, int ng) {
+    for (int k = threadIdx.x; k < LAB_GROUP_VALUES * ng; k += blockDim.x) {
+        const int v = k % LAB_GROUP_VALUES;
+        tab[k] = v == 3 ? INFINITY : (v == 4 ? -INFINITY : 0.0);
+    }
+}
+__device__ inline void lab_group_add(double *tab, const LabGroupSpec &G, const Params &P, double t, double x, double y,
+                                     double z, double ux, double uy, double uz, double w) {
+    const int g = lab_group_of(G, z, uz);
+    if (g < 0) return;
+    double L[8];
+    lab_of(P, t, x, y, z, ux, uy, uz, L);
+    double *e = tab + LAB_GROUP_VALUES * g;
+    atomicAdd(&e[0], 1.0);
+    atomicAdd(&e[1], w);
+    atomicAdd(&e[2], w * L[3]);
+    atomicMin(&e[3], L[3]);
+    atomicMax(&e[4], L[3]);
+    atomicAdd(&e[5], w * L[2]);
+    atomicAdd(&e[6], w * L[2] * L[2]);
+    atomicAdd(&e[7], w * L[0]);
+    atomicAdd(&e[8], w * L[0] * L[0]);
+    atomicAdd(&e[9], w * L[1]);
+    atomicAdd(&e[10], w * L[1] * L[1]);
+    atomicAdd(&e[11], w * L[4]);
+    atomicAdd(&e[12], w * L[4] * L[4]);
+    atomicAdd(&e[13], w * L[5]);
+    atomicAdd(&e[14], w * L[5] * L[5]);
+    atomicAdd(&e[15], w * L[7]);
+}
+// the block's nonempty groups into the global table
+__device__ inline void lab_table_flush(const double *tab, int ng, double *out) {
+    for (int k = threadIdx.x; k < LAB_GROUP_VALUES * ng; k += blockDim.x) {
+        const int g = k / LAB_GROUP_VALUES, v = k % LAB_GROUP_VALUES;
+        if (tab[LAB_GROUP_VALUES * g] == 0.0) continue;
+        if (v == 3)
+            atomicMin(&out[k], tab[k]);
+        else if (v == 4)
+            atomicMax(&out[k], tab[k]);
+        else
+            atomicAdd(&out[k], tab[k]);
+    }
+}
+
 __host__ __device__ inline int wrapi(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;

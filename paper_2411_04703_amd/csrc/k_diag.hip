@@ -236,6 +236,76 @@ __global__ void __launch_bounds__(DT) k_probe64(Params P, Part64 p, int64_t n, d
         for (int j = 0; j < 5; ++j) atomicAdd(&acc[j], s[j][0]);
 }
 
+// ---------------------------------------------------------------- lab frame (section 2)
+__global__ void __launch_bounds__(DT) k_lab64(Params P, Part64 p, int64_t n, double t, double *out) {
+    const int64_t q = (int64_t)blockIdx.x * DT + threadIdx.x;
+    if (q >= n) return;
+    double L[8];
+    lab_of(P, t, p.x[q], p.y[q], p.z[q], p.ux[q], p.uy[q], p.uz[q], L);
+    for (int k = 0; k < 8; ++k) out[(uint64_t)k * n + q] = L[k];
+}
+
+// FP32 mode: in place over the absolute FP64 phase space split_read wrote (rows x y z ux uy uz w)
+__global__ void __launch_bounds__(DT) k_lab_inplace(Params P, double *a, int64_t n, double t) {
+    const int64_t q = (int64_t)blockIdx.x * DT + threadIdx.x;
+    if (q >= n) return;
+    double L[8];
+    lab_of(P, t, a[q], a[n + q], a[2 * n + q], a[3 * n + q], a[4 * n + q], a[5 * n + q], L);
+    for (int k = 0; k < 8; ++k) a[(uint64_t)k * n + q] = L[k];
+}
+
+__global__ void k_lab_groups_init(double *out, int ng) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= LAB_GROUP_VALUES * ng) return;
+    const int v = k % LAB_GROUP_VALUES;
+    out[k] = v == 3 ? INFINITY : (v == 4 ? -INFINITY : 0.0);
+}
+
+__global__ void __launch_bounds__(DT) k_lab_groups64(Params P, LabGroupSpec G, Part64 p, int64_t n, double t,
+                                                     double *out) {
+    __shared__ double tab[LAB_GROUP_VALUES * LAB_GROUPS_MAX];
+    const int ng = G.nz * G.nu;
+    lab_table_clear(tab, ng);
+    __syncthreads();
+    for (int64_t q = (int64_t)blockIdx.x * DT + threadIdx.x; q < n; q += (int64_t)gridDim.x * DT)
+        if (p.alive[q]) lab_group_add(tab, G, P, t, p.x[q], p.y[q], p.z[q], p.ux[q], p.uy[q], p.uz[q], p.w[q]);
+    __syncthreads();
+    lab_table_flush(tab, ng, out);
+}
+
+pic_status lab_groups(Ctx &c, const LabGroupSpec &G, double *out) {
+    const int ng = G.nz * G.nu;
+    const double t = (double)c.step * c.P.dt;
+    hipLaunchKernelGGL(k_lab_groups_init, dim3(nblocks(LAB_GROUP_VALUES * ng, DT)), dim3(DT), 0, c.st, out, ng);
+    if (c.precision == PIC_FP64_PLAIN) {
+        if (c.nb_slots)
+            hipLaunchKernelGGL(k_lab_groups64, dim3(std::min(nblocks(c.nb_slots, DT), 1024)), dim3(DT), 0, c.st, c.P,
+                               G, c.b64, c.nb_slots, t, out);
+    } else {
+        split_lab_groups(c, G, t, out);
+    }
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    return PIC_OK;
+}
+
+pic_status lab_beam(Ctx &c, double *out, int64_t *n) {
+    const double t = (double)c.step * c.P.dt;
+    if (c.precision == PIC_FP64_PLAIN) {
+        *n = c.nb_slots;
+        if (out && c.nb_slots)
+            hipLaunchKernelGGL(k_lab64, dim3(nblocks(c.nb_slots, DT)), dim3(DT), 0, c.st, c.P, c.b64, c.nb_slots, t,
+                               out);
+    } else {
+        split_read(c, 0, nullptr, nullptr, n);
+        if (out && *n) {
+            split_read(c, 0, out, nullptr, n);
+            hipLaunchKernelGGL(k_lab_inplace, dim3(nblocks(*n, DT)), dim3(DT), 0, c.st, c.P, out, *n, t);
+        }
+    }
+    PIC_HIP(c, hipStreamSynchronize(c.st));
+    return PIC_OK;
+}
+
 // after a step (c.step, c.k0 already advanced): sample the beam particles whose lab time passed the probe's
 void probe_step(Ctx &c) {
     const double t1 = (double)c.step * c.P.dt;

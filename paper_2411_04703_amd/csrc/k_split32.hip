@@ -1973,6 +1973,43 @@ __global__ void k_split_probe(Params P, int64_t k0, Part32 in, const int64_t *of
         for (int j = 0; j < 5; ++j) atomicAdd(&acc[j], s[j][0]);
 }
 
+// lab-frame groups of the binned beam: blocks stride over the bins (and the overflow tail, "bin" nbins)
+__global__ void __launch_bounds__(256) k_split_lab_groups(Params P, LabGroupSpec G, int64_t k0, Part32 in,
+                                                          const int64_t *off, const int32_t *cnt, int64_t ovf_start,
+                                                          const int32_t *ovf, int64_t ovf_cap, double t, double *out) {
+    __shared__ double tab[LAB_GROUP_VALUES * LAB_GROUPS_MAX];
+    const int ng = G.nz * G.nu;
+    lab_table_clear(tab, ng);
+    __syncthreads();
+    for (int b = blockIdx.x; b <= P.nbins; b += gridDim.x) {
+        int64_t s0, n;
+        if (b < P.nbins) {
+            s0 = off[b];
+            n = min((int64_t)cnt[b], off[b + 1] - off[b]);
+        } else {
+            s0 = ovf_start;
+            n = min((int64_t)*ovf, ovf_cap);
+        }
+        for (int64_t j = threadIdx.x; j < n; j += 256) {
+            const int64_t q = s0 + j;
+            int i, jj, l;
+            unpack_cell(P, in.cell[q], i, jj, l);
+            lab_group_add(tab, G, P, t, (double)i + (double)in.ox[q], (double)jj + (double)in.oy[q],
+                          (double)(k0 + l) + (double)in.oz[q], in.ux[q], in.uy[q], in.uz[q], in.w[q]);
+        }
+    }
+    __syncthreads();
+    lab_table_flush(tab, ng, out);
+}
+
+void split_lab_groups(Ctx &c, const LabGroupSpec &G, double t, double *out) {
+    SplitState &X = SS(c);
+    const Store &S = X.s[0];
+    const int cur = c.cur32;
+    hipLaunchKernelGGL(k_split_lab_groups, dim3(std::min(c.P.nbins + 1, 1024)), dim3(256), 0, c.st, c.P, G, c.k0,
+                       S.buf[cur], S.off[cur], S.cnt[cur], S.bin_slots, S.ovf[cur], S.ovf_cap, t, out);
+}
+
 void split_probe(Ctx &c, double *acc) {
     SplitState &X = SS(c);
     const Store &S = X.s[0];

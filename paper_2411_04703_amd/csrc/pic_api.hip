@@ -813,8 +813,26 @@ pic_status pic_read(pic_ctx *c, int32_t which, void *dst, int64_t *count) {
         PIC_HIP(*c, hipStreamSynchronize(c->st));
         return PIC_OK;
     }
+    if (which == PIC_A_BEAM_LAB) {
+        int64_t n = 0;
+        pic_status st = lab_beam(*c, nullptr, &n);
+        if (count) *count = n;
+        if (st != PIC_OK || !dst || n == 0) return st;
+        return lab_beam(*c, (double *)dst, &n);
+    }
     c->err = "pic_read: unknown array";
     return PIC_EINVAL;
+}
+
+pic_status pic_lab_groups(pic_ctx *c, const pic_lab_groups_spec *spec, void *dst) {
+    if (!c || !spec || !dst) return PIC_EINVAL;
+    if (spec->nz < 1 || spec->nu < 1 || (int64_t)spec->nz * spec->nu > LAB_GROUPS_MAX || !(spec->dz > 0.0) ||
+        !(spec->du > 0.0) || !std::isfinite(spec->z_lo) || !std::isfinite(spec->u_lo)) {
+        c->err = "pic_lab_groups: need dz, du > 0, finite lower edges and 1 <= nz * nu <= 256 groups";
+        return PIC_EINVAL;
+    }
+    LabGroupSpec G{spec->z_lo, spec->dz, spec->u_lo, spec->du, spec->nz, spec->nu};
+    return lab_groups(*c, G, (double *)dst);
 }
 
 pic_status pic_write(pic_ctx *c, int32_t which, const void *src, int64_t count) {

@@ -140,11 +140,14 @@ pic_status split_inject_and_swap(Ctx &c, int64_t l0, int64_t l1, double t, int64
 pic_status split_check(Ctx &c);  // bin capacity check + re-layout (synchronising)
 void split_read(Ctx &c, int species, double *dst7, int32_t *alive, int64_t *n);
 void split_probe(Ctx &c, double *acc);  // lab-frame probe over the binned beam
+void split_lab_groups(Ctx &c, const LabGroupSpec &G, double t, double *out);  // lab-frame groups of the binned beam
 
 // diagnostics (k_diag.hip)
 pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *out);
 void beam_rho(Ctx &c, double *rho);  // beam charge on the nodes (ring order), added into rho
 void probe_step(Ctx &c);             // lab-frame probe: sample the beam particles that crossed its lab time
+pic_status lab_beam(Ctx &c, double *out, int64_t *n);                   // the beam's lab phase space (8 rows)
+pic_status lab_groups(Ctx &c, const LabGroupSpec &G, double *out);      // its groups (16 values each)
 
 // initial beam self-field and the faded neutralising charge (k_initfield.hip)
 pic_status init_beam_fields(Ctx &c);

@@ -111,8 +111,9 @@ class Sim:
         n = C.c_int64()
         _check(self.L, self.ctx, self.L.pic_read(self.ctx, k, None, C.byref(n)), "pic_read")
         alive = k in (abi.PIC_A_BEAM_ALIVE, abi.PIC_A_PLASMA_ALIVE)
-        if k in (abi.PIC_A_BEAM, abi.PIC_A_PLASMA):
-            t = torch.empty((7, max(n.value, 0)), dtype=torch.float64, device=self.device)
+        if k in (abi.PIC_A_BEAM, abi.PIC_A_PLASMA, abi.PIC_A_BEAM_LAB):
+            t = torch.empty((8 if k == abi.PIC_A_BEAM_LAB else 7, max(n.value, 0)), dtype=torch.float64,
+                            device=self.device)
         else:
             t = torch.empty(max(n.value, 0), dtype=torch.int32 if alive else torch.float64, device=self.device)
         if n.value:
@@ -160,6 +161,21 @@ class Sim:
         out = (C.c_double * 5)()
         _check(self.L, self.ctx, self.L.pic_lab_probe_read(self.ctx, out), "pic_lab_probe_read")
         return dict(zip(("w", "c", "s", "z", "zz"), list(out)))
+
+    def beam_lab(self) -> dict:
+        """The beam's lab-frame phase space at the current boosted time, each particle at its own lab time."""
+        a = self.read(abi.PIC_A_BEAM_LAB).cpu().numpy()
+        out = {k: a[i] for i, k in enumerate(("x", "y", "z", "t", "ux", "uy", "uz", "gamma"))}
+        out["alive"] = self.read(abi.PIC_A_BEAM_ALIVE).cpu().numpy()
+        return out
+
+    def lab_groups(self, z_lo, dz, nz, u_lo=-1e300, du=1e308, nu=1) -> np.ndarray:
+        """Lab-frame sums of the beam grouped by boosted z and u_z slices: (nz * nu, 16) array."""
+        spec = abi.pic_lab_groups_spec(float(z_lo), float(dz), float(u_lo), float(du), int(nz), int(nu))
+        out = torch.empty((nz * nu, abi.PIC_LAB_GROUP_VALUES), dtype=torch.float64, device=self.device)
+        _check(self.L, self.ctx, self.L.pic_lab_groups(self.ctx, C.byref(spec), C.c_void_p(out.data_ptr())),
+               "pic_lab_groups")
+        return out.cpu().numpy()
 
     def lambda_len(self) -> int:
         return int(self.L.pic_lambda_len(self.ctx))
