@@ -1,7 +1,11 @@
 // k_split32.hip -- FP32 split-precision path.
 //
 // Particles: int32 logical cell index (i + nx (j + ny l), l = window plane)
-// plus FP32 offsets in [0, 1), FP32 momenta and weight: 32 bytes each, SoA.
+// plus FP32 offsets from the cell's centre in [-1/2, 1/2) (position = cell +
+// 1/2 + offset), FP32 momenta and weight: 32 bytes each, SoA.  Offsets from
+// the centre keep the representation mirror-symmetric: a carry into either
+// neighbour is exact, a particle at rest at the centre has offset 0, and the
+// coarsest offset step is 2^-25 of a cell.
 // They are kept binned by cell tile ("bins") in two buffers; every step reads
 // the current buffer and appends each surviving particle to its destination
 // bin in the other buffer (wave-aggregated slot reservation), so the bins are
@@ -276,6 +280,11 @@ __device__ inline int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i -
 template <bool NY1 = false> __device__ inline int64_t near_cell(const Params &P, int i, int j, int p) {
     return (int64_t)wrap1(i, P.nx) + (int64_t)P.nx * ((NY1 ? (int64_t)0 : (int64_t)wrap1(j, P.ny)) + (int64_t)P.ny * p);
 }
+// the same in 32 bits: an FP32-mode grid has at most 2^31 cells (its cell index packs into 31 bits)
+template <bool NY1 = false> __device__ inline uint32_t near_cell32(const Params &P, int i, int j, int p) {
+    return (uint32_t)wrap1(i, P.nx) +
+           (uint32_t)P.nx * ((NY1 ? 0u : (uint32_t)wrap1(j, P.ny)) + (uint32_t)P.ny * (uint32_t)p);
+}
 
 
 // number of valid particles of bin b in a store
@@ -320,10 +329,11 @@ __device__ inline void load_particle(const Part32 &in, int64_t s, const Params &
     q.id = id_in ? gbl(id_in)[s] : 0;
 }
 
-// undulator field at logical plane l: the plane's phase and envelope argument in
-// FP64, the in-cell phase advance k_u gR oz in FP32 by angle addition
+// undulator field at the centre of logical plane l's cells: the phase and envelope
+// argument there in FP64, the in-cell phase advance k_u gR oz (oz the centred
+// offset) in FP32 by angle addition
 __device__ inline void ext_plane(const Params &P, int64_t k0, int l, double t, double &a_l, float &c, float &s) {
-    a_l = P.gR * ((double)(k0 + l) - P.zoff + P.bR * t) - P.z0u;
+    a_l = P.gR * ((double)(k0 + l) + 0.5 - P.zoff + P.bR * t) - P.z0u;
     double sn, cs;
     sincos(P.ku * a_l, &sn, &cs);
     c = (float)cs;
@@ -382,15 +392,15 @@ __device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
     e.cross = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const int n0 = X0[d] >= 0.5f ? 1 : 0;
-        const int n1 = (int)floorf(X1[d] + 0.5f);
+        const int n0 = X0[d] >= 0.0f ? 1 : 0;
+        const int n1 = (int)floorf(X1[d] + 1.0f);
         const int lo = n0 < n1 ? n0 : n1;
         e.base[d] = lo - 1;
         e.cross |= n0 != n1 ? 1 << d : 0;
         // the three nonzero weights around each nearest node, placed in the window
         float w0[3], w1[3];
-        weights3<float>(X0[d] - (float)n0, w0);
-        weights3<float>(X1[d] - (float)n1, w1);
+        weights3<float>(X0[d] - ((float)n0 - 0.5f), w0);  // offset from the node, one rounding
+        weights3<float>(X1[d] - ((float)n1 - 0.5f), w1);
         const bool h0 = n0 > lo, h1 = n1 > lo;  // window shifted by one node for this position
         float S1[4];
         e.S0[d][0] = h0 ? 0.0f : w0[0];
@@ -478,21 +488,19 @@ template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, fl
     esk_component<2, DEP>(e, f, fscale, fn);
 }
 
-// carry new offsets into the cell, apply the window shift; false if the particle left the band
+// carry new offsets into the cell, apply the window shift; false if the particle left the band.
+// Offsets are taken from the cell's centre, in [-1/2, 1/2); a move is less than a cell, so a
+// new offset lies in [-3/2, 3/2) and the carry o -+ 1 is exact either way (Sterbenz).
 __device__ inline bool renormalise(const Params &P, const StepCtx &S, PState &q) {
     int dc[3];
     for (int d = 0; d < 3; ++d) {
         dc[d] = 0;
-        if (q.o[d] >= 1.0f) {
+        if (q.o[d] >= 0.5f) {
             q.o[d] -= 1.0f;
             dc[d] = 1;
-        } else if (q.o[d] < 0.0f) {
+        } else if (q.o[d] < -0.5f) {
             q.o[d] += 1.0f;
             dc[d] = -1;
-            if (q.o[d] >= 1.0f) {  // a tiny negative offset rounded up to one cell
-                q.o[d] = 0.0f;
-                dc[d] = 0;
-            }
         }
     }
     q.i += dc[0];
@@ -573,9 +581,9 @@ template <class FA> __device__ inline void gather6(const FA &fa, const float o[3
     int bI[3], bH[3];
     const int rel[3] = {x0, y0, z0};
     for (int d = 0; d < 3; ++d) {
-        int nn = o[d] >= 0.5f ? 1 : 0;
-        weights3<float>(o[d] - (float)nn, wI[d]);
-        weights3<float>(o[d] - 0.5f, wH[d]);
+        int nn = o[d] >= 0.0f ? 1 : 0;                        // nearest integer node: cell + nn
+        weights3<float>(o[d] - ((float)nn - 0.5f), wI[d]);      // offset from it, one rounding
+        weights3<float>(o[d], wH[d]);                           // the cell's centre is a half node
         bI[d] = rel[d] + nn - 1;  // first integer node
         bH[d] = rel[d] - 1;       // first half node
     }
@@ -616,8 +624,8 @@ __device__ inline bool advance(const Params &P, float EB[6], bool ext, double a_
 // ---------------------------------------------------------------- untiled (global memory) update
 __device__ inline bool particle_global(const Params &P, const StepCtx &S, const float *const *F6, long long *Jx,
                                        long long *Jy, long long *Jz, PState &q, int32_t *flags) {
-    if (!(q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f && q.o[2] >= 0.0f && q.o[2] < 1.0f &&
-          q.l >= 3 && q.l < P.nz - 4)) {
+    if (!(q.o[0] >= -0.5f && q.o[0] < 0.5f && q.o[1] >= -0.5f && q.o[1] < 0.5f && q.o[2] >= -0.5f &&
+          q.o[2] < 0.5f && q.l >= 3 && q.l < P.nz - 4)) {
         atomicOr(flags, DFLAG_NONFINITE);
         return false;
     }
@@ -807,7 +815,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                 const int bc = k / G::FX, a = k - bc * G::FX, c = bc / G::FY, b = bc - c * G::FY;
                 int l = I.t0z - 1 + c;
                 l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
-                const int64_t o = near_cell<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+                const uint32_t o = near_cell32<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
                 for (int qq = 0; qq < 3; ++qq) lds_load(F6[qq] + o, Fs + qq * G::NF + r * SST + wbase);
             }
@@ -820,7 +828,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                 const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
                 int l = I.t0z - 1 + c;
                 l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);
-                const int64_t o = near_cell<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+                const uint32_t o = near_cell32<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
 #pragma unroll
                 for (int qq = 0; qq < 3; ++qq) lds_load(F6[3 + qq] + o, Bs + qq * G::NE + r * SST + wbase);
             }
@@ -886,8 +894,8 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                     lj = q.j - I.t0y;
                     lk = q.l - I.t0z;
                     const bool inside = li >= 0 && li < TX && lj >= 0 && lj < TY && lk >= 0 && lk < TZ &&
-                                        q.o[0] >= 0.0f && q.o[0] < 1.0f && q.o[1] >= 0.0f && q.o[1] < 1.0f &&
-                                        q.o[2] >= 0.0f && q.o[2] < 1.0f;
+                                        q.o[0] >= -0.5f && q.o[0] < 0.5f && q.o[1] >= -0.5f &&
+                                        q.o[1] < 0.5f && q.o[2] >= -0.5f && q.o[2] < 0.5f;
                     if (!inside) {
                         // cannot happen: every binned particle was appended to the bin of its cell
                         atomicOr(flags, DFLAG_BIN_LOST);
@@ -964,40 +972,50 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                     load_raw(iop.s[I.sp].in, I.b0 + I.start + tid, nx, REC ? iop.id[I.sp].in : nullptr);
             }
         }
-        // flush nonzero LDS currents with global 64-bit integer atomics, clearing the boxes
-        if (C.bin >= 0)
-            for (int k = tid; k < G::NJ; k += SST) {
-                const long long v = Js[k];
-                if (v == 0) continue;
-                Js[k] = 0;
-                int kk = k, x, y, z;
-                long long *J;
-                if (kk < G::NJX) {
-                    const int yz = kk / G::XX;
-                    x = kk - yz * G::XX;
-                    z = yz / G::XY;
-                    y = yz - z * G::XY;
-                    J = Jx;
-                } else if (kk < G::NJX + G::NJY) {
-                    kk -= G::NJX;
-                    const int yz = kk / G::YX;
-                    x = kk - yz * G::YX;
-                    z = yz / G::YY;
-                    y = yz - z * G::YY;
-                    J = Jy;
-                } else {
-                    kk -= G::NJX + G::NJY;
-                    const int yz = kk / G::ZX;
-                    x = kk - yz * G::ZX;
-                    z = yz / G::ZY;
-                    y = yz - z * G::ZY;
-                    J = Jz;
+        // flush nonzero LDS currents with global 64-bit integer atomics, clearing the boxes.
+        // Thread t takes columns t and t + SST of the three boxes' (x, y) footprints and walks
+        // their planes: a column's global offset is formed once, a plane's is wave-uniform.
+        if (C.bin >= 0) {
+            constexpr int CX = G::XX * G::XY, CY = G::YX * G::YY, CZ = G::ZX * G::ZY, NCOL = CX + CY + CZ;
+            constexpr int NPMAX = G::XZ > G::ZZ ? G::XZ : G::ZZ;
+            static_assert(NCOL <= 2 * SST && G::XZ == G::YZ, "two columns per thread");
+            const uint32_t pl = (uint32_t)P.nx * (uint32_t)P.ny;
+#pragma unroll 1
+            for (int r = 0; r < 2; ++r) {
+                const int g = tid + r * SST;
+                if (g < NCOL) {
+                    int x, y, np, stride, lb;
+                    long long *J;
+                    if (g < CX) {
+                        y = g / G::XX;
+                        x = g - y * G::XX;
+                        np = G::XZ, stride = CX, lb = g, J = Jx;
+                    } else if (g < CX + CY) {
+                        const int h = g - CX;
+                        y = h / G::YX;
+                        x = h - y * G::YX;
+                        np = G::YZ, stride = CY, lb = G::NJX + h, J = Jy;
+                    } else {
+                        const int h = g - CX - CY;
+                        y = h / G::ZX;
+                        x = h - y * G::ZX;
+                        np = G::ZZ, stride = CZ, lb = G::NJX + G::NJY + h, J = Jz;
+                    }
+                    const uint32_t col = near_cell32<TY == 1>(P, C.t0x - 2 + x, C.t0y - 2 + y, 0);
+#pragma unroll 1
+                    for (int z = 0; z < NPMAX; ++z) {
+                        if (z >= np) continue;
+                        const long long v = Js[lb + z * stride];
+                        if (v == 0) continue;
+                        Js[lb + z * stride] = 0;
+                        const int l = C.t0z - 2 + z;
+                        if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
+                        const uint32_t o = col + pl * (uint32_t)ring_plane(l, S.k0r, P.nz);
+                        atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
+                    }
                 }
-                const int l = C.t0z - 2 + z;
-                if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
-                const int64_t o = near_cell<TY == 1>(P, C.t0x - 2 + x, C.t0y - 2 + y, ring_plane(l, S.k0r, P.nz));
-                atomicAdd((unsigned long long *)&J[o], (unsigned long long)v);
             }
+        }
         cur = next;
     }
 }
@@ -1331,11 +1349,11 @@ __global__ void k_beam_init32(Params P, const double *g, int64_t n, double sx, d
             s.i = min((int)fx, P.nx - 1);
             s.j = min((int)fy, P.ny - 1);
             s.l = (int)fz;
-            s.o[0] = (float)(x - fx);
-            s.o[1] = (float)(y - fy);
-            s.o[2] = (float)(z - fz);
+            s.o[0] = (float)(x - fx - 0.5);  // from the cell's centre (x - fx and the 0.5 exact in FP64)
+            s.o[1] = (float)(y - fy - 0.5);
+            s.o[2] = (float)(z - fz - 0.5);
             for (int d = 0; d < 3; ++d)
-                if (s.o[d] >= 1.0f) s.o[d] = 0.99999994f;  // FP32 rounding of x - floor(x) up to 1
+                if (s.o[d] >= 0.5f) s.o[d] = 0.49999997f;  // FP32 rounding up to the cell's edge
             s.u[0] = (float)ux;
             s.u[1] = (float)uy;
             s.u[2] = (float)uzb;
@@ -1396,10 +1414,10 @@ __global__ void k_inject32(Params P, int64_t l0, int64_t total, double t, int64_
         double z = sheet_z(l, P.ppz, P.bR, t) - (double)k0;  // logical
         double fz = floor(z);
         s.l = (int)fz;
-        s.o[0] = (float)((a + 0.5) / P.ppx);
-        s.o[1] = (float)((b + 0.5) / P.ppy);
-        s.o[2] = (float)(z - fz);
-        if (s.o[2] >= 1.0f) s.o[2] = 0.99999994f;
+        s.o[0] = (float)((a + 0.5) / P.ppx - 0.5);  // from the cell's centre
+        s.o[1] = (float)((b + 0.5) / P.ppy - 0.5);
+        s.o[2] = (float)(z - fz - 0.5);
+        if (s.o[2] >= 0.5f) s.o[2] = 0.49999997f;
         s.u[0] = 0.0f;
         s.u[1] = 0.0f;
         s.u[2] = (float)(-P.uR);
@@ -1649,9 +1667,9 @@ __global__ void k_split_export(Params P, int64_t k0, Part32 in, const int32_t *i
         const int64_t s = s0 + k, d = in_id[s];
         int i, j, l;
         unpack_cell(P, in.cell[s], i, j, l);
-        dst.x[d] = i + (double)in.ox[s];
-        dst.y[d] = j + (double)in.oy[s];
-        dst.z[d] = (double)(k0 + l) + (double)in.oz[s];
+        dst.x[d] = (i + 0.5) + (double)in.ox[s];
+        dst.y[d] = (j + 0.5) + (double)in.oy[s];
+        dst.z[d] = ((double)(k0 + l) + 0.5) + (double)in.oz[s];
         dst.ux[d] = in.ux[s];
         dst.uy[d] = in.uy[s];
         dst.uz[d] = in.uz[s];
@@ -1801,7 +1819,8 @@ __global__ void k_split_out(Params P, int64_t k0, Part32 in, const int64_t *off,
         }
         int i, j, l;
         unpack_cell(P, in.cell[s], i, j, l);
-        double v[7] = {i + (double)in.ox[s], j + (double)in.oy[s], (double)(k0 + l) + (double)in.oz[s],
+        double v[7] = {(i + 0.5) + (double)in.ox[s], (j + 0.5) + (double)in.oy[s],
+                       ((double)(k0 + l) + 0.5) + (double)in.oz[s],
                        (double)in.ux[s], (double)in.uy[s], (double)in.uz[s], (double)in.w[s]};
         for (int q = 0; q < nout; ++q) dst[q * stride + d] = v[q];
     }
@@ -1829,8 +1848,8 @@ __global__ void k_split_rho(Params P, int64_t k0, int k0r, Part32 in, const int6
         int lo[3];
         const int base[3] = {i, j, l};
         for (int d = 0; d < 3; ++d) {
-            int nn = o[d] >= 0.5f ? 1 : 0;
-            weights3<double>((double)o[d] - nn, w[d]);
+            int nn = o[d] >= 0.0f ? 1 : 0;
+            weights3<double>((double)o[d] + 0.5 - nn, w[d]);
             lo[d] = base[d] + nn - 1;
         }
         double qw = -(double)in.w[s];
@@ -1960,7 +1979,8 @@ __global__ void k_split_probe(Params P, int64_t k0, Part32 in, const int64_t *of
         const int64_t q = s0 + j;
         int i, jj, l;
         unpack_cell(P, in.cell[q], i, jj, l);
-        probe_particle(P, (double)(k0 + l) + (double)in.oz[q], in.ux[q], in.uy[q], in.uz[q], in.w[q], t1, T, k, v);
+        probe_particle(P, ((double)(k0 + l) + 0.5) + (double)in.oz[q], in.ux[q], in.uy[q], in.uz[q], in.w[q], t1, T,
+                       k, v);
     }
     for (int j = 0; j < 5; ++j) s[j][threadIdx.x] = v[j];
     __syncthreads();
@@ -1994,8 +2014,8 @@ __global__ void __launch_bounds__(256) k_split_lab_groups(Params P, LabGroupSpec
             const int64_t q = s0 + j;
             int i, jj, l;
             unpack_cell(P, in.cell[q], i, jj, l);
-            lab_group_add(tab, G, P, t, (double)i + (double)in.ox[q], (double)jj + (double)in.oy[q],
-                          (double)(k0 + l) + (double)in.oz[q], in.ux[q], in.uy[q], in.uz[q], in.w[q]);
+            lab_group_add(tab, G, P, t, (i + 0.5) + (double)in.ox[q], (jj + 0.5) + (double)in.oy[q],
+                          ((double)(k0 + l) + 0.5) + (double)in.oz[q], in.ux[q], in.uy[q], in.uz[q], in.w[q]);
         }
     }
     __syncthreads();
