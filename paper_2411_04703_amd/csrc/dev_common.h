@@ -28,7 +28,6 @@ struct Params {
     int cbx, cby, lgx, lgy, lgz, pad3;
     // mobile ions: mass in electron masses, and the pusher's half-step factor 0.5 (q/m) dt = 0.5 dt / mi
     double mi, ahi;
-    float idt32;  // FP32 mode: 1 / dt rounded to FP32 (the deposit's w / dt is w * idt32)
     int pad4;
 };
 

@@ -133,11 +133,14 @@ __global__ void __launch_bounds__(DT) k_rho64(Params P, int64_t k0, int k0r, Par
 }
 
 // ion charge profile (logical planes): sum over sheets of w ppx ppy S(k - z_l)
-__global__ void k_rho_ion(Params P, int64_t sh_lo, int64_t ns, double t, int64_t k0, double *prof) {
+// w32: the FP32 mode's ions carry their electrons' FP32-rounded weight
+__global__ void k_rho_ion(Params P, int64_t sh_lo, int64_t ns, double t, int64_t k0, double *prof, int w32) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= ns) return;
     int64_t l = sh_lo + q;
-    double w = sheet_weight(P, l) * (double)(P.ppx * P.ppy);
+    double w = sheet_weight(P, l);
+    if (w32) w = (double)(float)w;
+    w *= (double)(P.ppx * P.ppy);
     if (w == 0.0) return;
     double z = sheet_z(l, P.ppz, P.bR, t);
     double nn = floor(z + 0.5), ws[3];
@@ -454,7 +457,7 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
         }
         if (P.ions && c.sh_hi > c.sh_lo)
             hipLaunchKernelGGL(k_rho_ion, dim3(nblocks(c.sh_hi - c.sh_lo, 128)), dim3(128), 0, c.st, P, c.sh_lo,
-                               c.sh_hi - c.sh_lo, o->t, c.k0, ion);
+                               c.sh_hi - c.sh_lo, o->t, c.k0, ion, c.precision != PIC_FP64_PLAIN);
         launch_neutraliser_rho(c, rho);
         int nblk = nblocks(P.nc, DT);
         int64_t dk = c.k0 - c.rprev_k0;

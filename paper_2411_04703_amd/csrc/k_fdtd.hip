@@ -154,9 +154,13 @@ template void launch_mur_shift<float, long long>(const Params &, int, int, int, 
 // over a transversely uniform lattice, their Esirkepov current is J_z(z) only:
 // per sheet the running sum of -q w ppx ppy (S(z1 - k) - S(z0 - k)) / dt.
 // One thread per sheet, contributions added into a logical-plane profile.
+// w32: the FP32 mode's ions, which carry the FP32-rounded weight of their sheet's electrons
+// (the weight the electrons are stored with), so that the cold lattice is exactly neutral
+// and current-free in either mode
 __device__ inline void ion_sheet_terms(const Params &P, int64_t l, double t0, double t1, int64_t k0, double out[4],
-                                       int &lbase) {
+                                       int &lbase, bool w32) {
     double w = sheet_weight(P, l);
+    if (w32) w = (double)(float)w;
     double z0 = sheet_z(l, P.ppz, P.bR, t0), z1 = sheet_z(l, P.ppz, P.bR, t1);
     int64_t b = (int64_t)floor(z0 + 0.5) - 2;
     double acc = 0.0, f = -w * (double)(P.ppx * P.ppy) / P.dt;
@@ -172,7 +176,7 @@ __global__ void k_ion64(Params P, int64_t sh_lo, int64_t ns, double t0, double t
     if (q >= ns) return;
     double v[4];
     int lb;
-    ion_sheet_terms(P, sh_lo + q, t0, t1, k0, v, lb);
+    ion_sheet_terms(P, sh_lo + q, t0, t1, k0, v, lb, false);
     for (int m = 0; m < 4; ++m)
         if (v[m] != 0.0 && lb + m >= 0 && lb + m < P.nz) atomicAdd(&jion[lb + m], v[m]);
 }
@@ -183,7 +187,7 @@ __global__ void k_ion_fixed(Params P, int64_t sh_lo, int64_t ns, double t0, doub
     if (q >= ns) return;
     double v[4];
     int lb;
-    ion_sheet_terms(P, sh_lo + q, t0, t1, k0, v, lb);
+    ion_sheet_terms(P, sh_lo + q, t0, t1, k0, v, lb, true);
     for (int m = 0; m < 4; ++m) {
         double s = v[m] * P.fscale;
         if (fabs(s) > 4.0e18) atomicOr(flags, DFLAG_FIXED_OVERFLOW);

@@ -306,8 +306,8 @@ __device__ inline long long to_fixed(double x, double y) {
 // Every Esirkepov contribution of a particle is f P_c[m] A_c[a][b] with
 // |P_c| <= 1 and 0 <= A_c <= 9/16, so |f| bounds them all: one range check per
 // particle (false also for a non-finite f)
-__device__ inline bool fixed_ok(float f, double fscale) {
-    return fabs((double)f) * fscale < 2251799813685248.0;  // 2^51
+__device__ inline bool fixed_ok(double f, double fscale) {
+    return fabs(f) * fscale < 2251799813685248.0;  // 2^51
 }
 
 // ---------------------------------------------------------------- particle math
@@ -423,34 +423,47 @@ __device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
 // addresses are one per-particle base plus an immediate offset).
 // Per component c the current factorises:
 //   J_c(m, a, b) = f P_c[m] A_c[a][b],  P_c[m] = sum_{m' <= m} DS_c[m'],
-//   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3),
+//   A_c[a][b] = S0_a (S0_b + DS_b / 2) + DS_a (S0_b / 2 + DS_b / 3)
+//             = (S0_a + DS_a / 2) S0_b + (S0_a / 2 + DS_a / 3) DS_b,
 // and P_c[2] = -DS_c[3] (the DS sum to zero), exactly zero without a crossing.
-// f P_c[m] 2^fs is exact in FP64 (a product of two FP32 numbers and a power of
-// two), so each value converted is the exact product of the three FP32 factors
-// f, P_c[m] and A_c[a][b], rounded once to the fixed point.
+// A_c is evaluated as the mean of its two factorised forms, so that it is the
+// same FP32 number with the axes a and b exchanged: the transverse currents J_x
+// (a, b = y, z) and J_y (a, b = z, x) then round alike, and an FP32 run keeps
+// the x-y mirror symmetry of the FP64 scheme (with one form only, J_x rounded
+// differently from J_y and the beam's sigma_x drifted from sigma_y by 1e-3 over
+// a 1000-step plasma run).  f = w / dt is formed in FP64; f P_c[m] 2^fs is one
+// FP64 product, and each value converted is that product times A_c rounded
+// once to the fixed point.
 // DEP 0 visits nonzero contributions only (one branch each); DEP 1 visits all
 // 48 of a component that moves along its axis; DEP 2 leaves out the window's
 // last node along an axis (m = 2, a = 3 or b = 3) when no lane of the wave
 // crosses there (wave-uniform branches).  The values visited differ only by
 // zeros, so the integer current sums are the same.
 template <int C, int DEP, typename F>
-__device__ inline void esk_component(const Esk &e, float f, double fscale, F &&fn) {
+__device__ inline void esk_component(const Esk &e, double f, double fscale, F &&fn) {
     constexpr int CA = C == 2 ? 0 : C + 1, CB = C == 0 ? 2 : C - 1;
     float Pm[3];
     Pm[0] = e.DS[C][0];
     Pm[1] = Pm[0] + e.DS[C][1];
     Pm[2] = -e.DS[C][3];
     if (DEP != 0 && Pm[0] == 0.0f && Pm[1] == 0.0f && Pm[2] == 0.0f) return;
-    const double fs = fscale * (double)f;  // exact: f times a power of two
+    const double fs = fscale * f;
     double Pd[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) Pd[m] = (double)Pm[m] * fs;  // exact: 24 x 24 significant bits
-    float ub[4], vb[4];
+    for (int m = 0; m < 3; ++m) Pd[m] = (double)Pm[m] * fs;
+    // u_d = S0_d + DS_d / 2, v_d = S0_d / 2 + DS_d / 3 along both cross axes
+    float ub[4], vb[4], ua[4], va[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         ub[b] = fmaf(0.5f, e.DS[CB][b], e.S0[CB][b]);
         vb[b] = fmaf(1.0f / 3.0f, e.DS[CB][b], 0.5f * e.S0[CB][b]);
+        ua[b] = fmaf(0.5f, e.DS[CA][b], e.S0[CA][b]);
+        va[b] = fmaf(1.0f / 3.0f, e.DS[CA][b], 0.5f * e.S0[CA][b]);
     }
+    // exchanging a and b swaps the two fmaf terms, whose sum is then the same number
+    auto Aab = [&](int a, int b) {
+        return 0.5f * (fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]) + fmaf(ua[a], e.S0[CB][b], va[a] * e.DS[CB][b]));
+    };
     if (DEP == 2) {
         const bool m2 = __any(e.cross & (1 << C)), a3 = __any(e.cross & (1 << CA)), b3 = __any(e.cross & (1 << CB));
 #pragma unroll
@@ -459,7 +472,7 @@ __device__ inline void esk_component(const Esk &e, float f, double fscale, F &&f
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (b == 3 && !b3) break;
-                const double A = (double)fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
+                const double A = (double)Aab(a, b);
                 fn(C, 0, a, b, to_fixed(A, Pd[0]));
                 fn(C, 1, a, b, to_fixed(A, Pd[1]));
                 if (m2) fn(C, 2, a, b, to_fixed(A, Pd[2]));
@@ -471,7 +484,7 @@ __device__ inline void esk_component(const Esk &e, float f, double fscale, F &&f
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            float A = fmaf(e.S0[CA][a], ub[b], e.DS[CA][a] * vb[b]);
+            const float A = Aab(a, b);
             if (DEP == 0 && A == 0.0f) continue;
             const double Ad = (double)A;
 #pragma unroll
@@ -480,7 +493,7 @@ __device__ inline void esk_component(const Esk &e, float f, double fscale, F &&f
         }
 }
 
-template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, float f, double fscale, F &&fn) {
+template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, double f, double fscale, F &&fn) {
     esk_component<0, DEP>(e, f, fscale, fn);
     __builtin_amdgcn_sched_barrier(0);
     esk_component<1, DEP>(e, f, fscale, fn);
@@ -643,7 +656,7 @@ __device__ inline bool particle_global(const Params &P, const StepCtx &S, const 
     Esk e;
     esk_setup(q.o, X1, e);
     long long *J[3] = {Jx, Jy, Jz};
-    const float fq = q.w * P.idt32;
+    const double fq = (double)q.w / P.dt;
     if (!fixed_ok(fq, P.fscale)) {
         atomicOr(flags, DFLAG_FIXED_OVERFLOW);
         return false;
@@ -886,7 +899,8 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                 // pushed: advanced (deposits its current); act: still in the band (appended)
                 bool act = base + tid < I.end, pushed = false;
                 PState q;
-                float X0[3] = {0.0f, 0.0f, 0.0f}, X1[3] = {0.0f, 0.0f, 0.0f}, fq = 0.0f;
+                float X0[3] = {0.0f, 0.0f, 0.0f}, X1[3] = {0.0f, 0.0f, 0.0f};
+                double fq = 0.0;
                 int li = 0, lj = 0, lk = 0;
                 if (act) {
                     unpack_raw(P, nx, q);
@@ -907,10 +921,10 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                             atomicOr(flags, DFLAG_NONFINITE);
                             act = false;
                         } else {
-                            fq = q.w * P.idt32;
+                            fq = (double)q.w / P.dt;
                             if (!fixed_ok(fq, P.fscale)) {
                                 atomicOr(flags, DFLAG_FIXED_OVERFLOW);
-                                fq = 0.0f;
+                                fq = 0.0;
                             }
                             for (int d = 0; d < 3; ++d) {
                                 X0[d] = q.o[d];

@@ -111,7 +111,6 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     P.mobile = P.has_plasma && p->ions == 2;
     P.mi = p->ion_mass > 0 ? p->ion_mass : kProtonMass;
     P.ahi = 0.5 * P.dt / P.mi;
-    P.idt32 = (float)(1.0 / P.dt);
     P.ppx = std::max(1, p->ppc[0]);
     P.ppy = std::max(1, p->ppc[1]);
     P.ppz = std::max(1, p->ppc[2]);

@@ -273,14 +273,18 @@ def test_fp32_deposit_per_component_against_oracle(case):
     """From zero fields one step gives E^1 = -dt J exactly (B^(1/2) = 0), so E^1 node by node is
     the deposited current.  Each component of the FP32 path's E^1 is compared, element by element,
     with the oracle's (FP64) at a bound derived from the FP32 arithmetic, not from the plasma's
-    cancelling gross current where it plays no part:
+    cancelling gross current where it plays no part.  A contribution is f P A (f = w / dt, formed
+    in FP64; |P| <= 1, 0 <= A <= 9/16).  In units of eps32: a shape weight is off by <= 1.25 (the
+    rounded offset from the node and three roundings of the polynomial), a shape difference by
+    <= 3, P (a sum of at most two) by <= 6.5, and A, the mean of its two factorised forms, by
+    <= 8.2 (each form's inputs and two roundings, then the mean); so one contribution is off by
+    <= f (6.5 * 9/16 + 8.2) eps32 < 13.5 eps32 f:
     * J_x, J_y: at the first step only beam particles move across (the plasma starts cold and feels
-      no field yet), and a particle's transverse contribution f P A (f = w / dt, A <= 9/16) carries
-      the FP32 error of P, a sum of at most three shape differences, each off by <= 8 eps32 (the
-      rounded end offset, the shape polynomials, the subtraction): |dJ| <= 13.5 eps32 sum |f| over
-      the particles whose window holds the node;
+      no field yet): |dJ| <= 13.5 eps32 sum |f| over the particles whose window holds the node;
     * J_z: the same per-particle bound over beam and plasma particles (the plasma's gross current
-      enters here, and only here), plus the ion sheets' fixed-point rounding;
+      enters here, and only here), which also covers the ion sheets: the FP32 mode's ions carry
+      their electrons' FP32-rounded weight (eps32 / 2 of the electrons' share), rounded once to
+      the fixed point per sheet and plane;
     * all: one 2^-(f+1) rounding of every contribution to the 64-bit fixed point, and the FP32
       rounding of the net value in the E update (eps32 |J|).
     Summed linearly over the particles this is a hard bound; the rounding errors of different
