@@ -245,6 +245,21 @@ typedef struct {
 } pic_diag_out;
 PIC_API pic_status pic_diag(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_diag_out *out);
 
+/* pic_diag for callers that cannot allocate device memory at all (code under
+ * graph capture, serving loops, harnesses that forbid it): the same
+ * diagnostics, bit for bit, with their per-block partial sums in a static
+ * device array of the library (4 MiB per GPU, PIC_DIAG_STATIC_DOUBLES
+ * doubles, set up by pic_init once per device and held until the process
+ * ends) instead of the context's arena.  Allocates nothing.  Needs the
+ * context's device current (PIC_EINVAL otherwise); PIC_ERANGE when the mask
+ * needs more partials than the array holds (13 per 256 beam particles, 2
+ * per 256 plasma slots or per FP32 bin, 3 per 256 cells with
+ * PIC_DIAG_GAUSS).  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU, from several threads or streams, race; serialise
+ * them.  Synchronising. */
+enum { PIC_DIAG_STATIC_DOUBLES = 1 << 19 };
+PIC_API pic_status pic_diag_static(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_diag_out *out);
+
 /* Named arrays in canonical order (fields: logical window planes, x fastest;
  * particles: FP64 mode in slot order, FP32 mode in bin order; FP32 positions
  * are returned as absolute FP64 coordinates).  dst: DEVICE buffer.  count

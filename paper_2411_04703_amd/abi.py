@@ -16,6 +16,7 @@ PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_ESTATE, PIC_ERANGE = 0, -1, -2,
 PIC_FP64_PLAIN, PIC_FP32_SPLIT = 0, 1
 PIC_BORIS, PIC_VAY, PIC_PUSHER_AUTO = 0, 1, -1
 PIC_DIAG_MOMENTS, PIC_DIAG_BUNCHING, PIC_DIAG_ENERGY, PIC_DIAG_GAUSS = 1, 2, 4, 8
+PIC_DIAG_STATIC_DOUBLES = 1 << 19
 PIC_A_EX, PIC_A_EY, PIC_A_EZ, PIC_A_BX, PIC_A_BY, PIC_A_BZ = range(6)
 PIC_A_BEAM, PIC_A_BEAM_ALIVE, PIC_A_PLASMA, PIC_A_PLASMA_ALIVE, PIC_A_BEAM_LAB = 16, 17, 18, 19, 20
 PIC_LAB_GROUP_VALUES = 16
@@ -93,7 +94,7 @@ class pic_diag_out(C.Structure):
 EXPORTS = ("pic_query_layout", "pic_derive", "pic_init", "pic_step", "pic_diag", "pic_read", "pic_write",
            "pic_get_state", "pic_set_state", "pic_lambda_len", "pic_adjoint_seed_bunching", "pic_adjoint_step",
            "pic_timing", "pic_timing_read", "pic_sync", "pic_free", "pic_last_error", "pic_state_to_fp64",
-           "pic_lab_probe", "pic_lab_probe_read", "pic_set_window_beta", "pic_lab_groups")
+           "pic_lab_probe", "pic_lab_probe_read", "pic_set_window_beta", "pic_lab_groups", "pic_diag_static")
 
 _lib = None
 
@@ -114,6 +115,7 @@ def load() -> C.CDLL:
     L.pic_init.argtypes = cfg + [C.c_void_p, C.c_uint64, P(C.c_void_p)]
     L.pic_step.argtypes = [C.c_void_p, C.c_int32]
     L.pic_diag.argtypes = [C.c_void_p, C.c_uint32, C.c_double, P(pic_diag_out)]
+    L.pic_diag_static.argtypes = [C.c_void_p, C.c_uint32, C.c_double, P(pic_diag_out)]
     L.pic_read.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, P(C.c_int64)]
     L.pic_write.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]
     L.pic_get_state.argtypes = [C.c_void_p, C.c_void_p]

@@ -5,22 +5,23 @@
 // frame change (transverse dynamics, charge; section 2) and reports the beam
 // modulation at the boosted undulator period and half of it (section 3); the
 // bunching factor |sum w exp(i k z')| / sum w is taken at fixed t' in the
-// boosted frame.  All sums are FP64 with per-block partials reduced on the
-// host in block order, so a diagnostic of a given particle order is
-// reproducible bit for bit.
+// boosted frame.  All sums are FP64 with per-block partials, reduced on the
+// device in a fixed order (k_reduce_partials), so a diagnostic of a given
+// particle order is reproducible bit for bit.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "pic_internal.h"
 
 namespace pic {
 
-void split_rho(Ctx &c, double *rho, int mask);       // k_split32.hip
-void split_plasma_kinetic(Ctx &c, double *out2);     // k_split32.hip
-int64_t split_beam_to64(Ctx &c, double *dst6);       // k_split32.hip
+void split_rho(Ctx &c, double *rho, int mask);                 // k_split32.hip
+int split_plasma_kinetic_partials(Ctx &c, double *red);        // k_split32.hip
+int64_t split_beam_to64(Ctx &c, double *dst6);                 // k_split32.hip
 
 constexpr int DT = 256;
 
@@ -212,13 +213,48 @@ __global__ void __launch_bounds__(DT) k_store_r(Params P, int k0r, FieldsT<T> f,
     rnew[q] = rv;
 }
 
-static void host_sum(Ctx &c, int nblk, int nv, std::vector<double> &acc) {
-    std::vector<double> h((size_t)nblk * nv);
-    hipMemcpyAsync(h.data(), c.red, 8 * (uint64_t)nblk * nv, hipMemcpyDeviceToHost, c.st);
+// The nv values of nblk per-block partials (red[b nv + k]) reduced in a fixed
+// order by one block: thread t takes the blocks [t m, (t + 1) m) in order, then
+// a fixed tree; the results overwrite red[0 .. nv).  OP 0 sums, OP 1 takes the
+// maximum with 0.
+constexpr int RED_MAX_NV = 16;
+template <int OP> __global__ void __launch_bounds__(DT) k_reduce_partials(double *red, int64_t nblk, int nv) {
+    __shared__ double s[DT];
+    const int64_t m = (nblk + DT - 1) / DT, b0 = (int64_t)threadIdx.x * m, b1 = min(b0 + m, nblk);
+    double acc[RED_MAX_NV];
+#pragma unroll
+    for (int k = 0; k < RED_MAX_NV; ++k) acc[k] = 0.0;
+    for (int64_t b = b0; b < b1; ++b)
+#pragma unroll
+        for (int k = 0; k < RED_MAX_NV; ++k)
+            if (k < nv) {
+                const double v = red[b * nv + k];
+                acc[k] = OP == 0 ? acc[k] + v : (acc[k] < v ? v : acc[k]);
+            }
+    __syncthreads();  // every partial read before red[0 .. nv) is overwritten
+    for (int k = 0; k < nv; ++k) {
+        s[threadIdx.x] = acc[k < RED_MAX_NV ? k : 0];
+        __syncthreads();
+        for (int h = DT / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                const double v = s[threadIdx.x + h];
+                s[threadIdx.x] = OP == 0 ? s[threadIdx.x] + v : (s[threadIdx.x] < v ? v : s[threadIdx.x]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) red[k] = s[0];
+        __syncthreads();
+    }
+}
+
+// reduce nblk partials of nv values in red and copy the nv results to acc (host)
+static void reduce_partials(Ctx &c, double *red, int64_t nblk, int nv, int op, double *acc) {
+    if (op == 0)
+        hipLaunchKernelGGL(k_reduce_partials<0>, dim3(1), dim3(DT), 0, c.st, red, nblk, nv);
+    else
+        hipLaunchKernelGGL(k_reduce_partials<1>, dim3(1), dim3(DT), 0, c.st, red, nblk, nv);
+    hipMemcpyAsync(acc, red, 8 * (uint64_t)nv, hipMemcpyDeviceToHost, c.st);
     hipStreamSynchronize(c.st);
-    acc.assign(nv, 0.0);
-    for (int b = 0; b < nblk; ++b)
-        for (int k = 0; k < nv; ++k) acc[k] += h[(size_t)b * nv + k];
 }
 
 // lab-frame probe over the live FP64 beam slots: each block's five sums added to acc
@@ -335,9 +371,27 @@ void beam_rho(Ctx &c, double *rho) {
     }
 }
 
-pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
+// partial sums run_diag needs in red (doubles)
+int64_t diag_partials(const Ctx &c, uint32_t mask) {
+    const Params &P = c.P;
+    const int64_t nb = c.precision == PIC_FP64_PLAIN ? c.nb_slots : c.beam.n_macro;
+    int64_t need = 13 * (int64_t)nblocks(std::max<int64_t>(nb, 1), DT);
+    if (mask & PIC_DIAG_ENERGY) need = std::max<int64_t>(need, 1024);
+    if (P.has_plasma)
+        need = std::max<int64_t>(need, 2 * (c.precision == PIC_FP64_PLAIN
+                                                ? (int64_t)nblocks(std::max<int64_t>(c.np_slots, 1), DT)
+                                                : (int64_t)P.nbins + 1));
+    if (mask & PIC_DIAG_GAUSS) need = std::max<int64_t>(need, 3 * (int64_t)nblocks(P.nc, DT));
+    return need;
+}
+
+pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o, double *red, int64_t red_cap) {
     memset(o, 0, sizeof *o);
     const Params &P = c.P;
+    if (diag_partials(c, mask) > red_cap) {
+        c.err = "diagnostics: more partial sums than the reduction buffer holds";
+        return PIC_ERANGE;
+    }
     o->t = (double)c.step * P.dt;
     o->step = (double)c.step;
     o->k0 = (double)c.k0;
@@ -364,13 +418,12 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
         bp.w = nullptr;
         bp.alive = nullptr;
     }
-    std::vector<double> m1;
+    double m1[13] = {0};
     if (nb > 0) {
         int nblk = nblocks(nb, DT);
-        hipLaunchKernelGGL(k_mom1, dim3(nblk), dim3(DT), 0, c.st, bp, nb, wconst, kb, c.red);
-        host_sum(c, nblk, 13, m1);
-    } else
-        m1.assign(13, 0.0);
+        hipLaunchKernelGGL(k_mom1, dim3(nblk), dim3(DT), 0, c.st, bp, nb, wconst, kb, red);
+        reduce_partials(c, red, nblk, 13, 0, m1);
+    }
     o->n_beam = m1[0];
     o->beam_lost = (double)c.beam.n_macro - m1[0];
     o->wsum = m1[1];
@@ -392,9 +445,9 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
         if (mask & PIC_DIAG_MOMENTS) {
             int nblk = nblocks(nb, DT);
             hipLaunchKernelGGL(k_mom2, dim3(nblk), dim3(DT), 0, c.st, bp, nb, wconst, mean[0], mean[1], mean[2],
-                               mean[3], mean[4], mean[5], c.red);
-            std::vector<double> m2;
-            host_sum(c, nblk, 8, m2);
+                               mean[3], mean[4], mean[5], red);
+            double m2[8];
+            reduce_partials(c, red, nblk, 8, 0, m2);
             for (int k = 0; k < 3; ++k) {
                 o->sigma[k] = sqrt(m2[k] / W);
                 o->usigma[k] = sqrt(m2[3 + k] / W);
@@ -407,23 +460,23 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
     }
     if (mask & PIC_DIAG_ENERGY) {
         int nblk = 1024;
-        std::vector<double> fe;
+        double fe[1];
         if (c.precision == PIC_FP64_PLAIN) {
             FieldsT<double> f;
             for (int k = 0; k < 3; ++k) {
                 f.E[k] = c.E64[k];
                 f.B[k] = c.B64[k];
             }
-            hipLaunchKernelGGL(k_fenergy<double>, dim3(nblk), dim3(DT), 0, c.st, f, P.nc, c.red);
+            hipLaunchKernelGGL(k_fenergy<double>, dim3(nblk), dim3(DT), 0, c.st, f, P.nc, red);
         } else {
             FieldsT<float> f;
             for (int k = 0; k < 3; ++k) {
                 f.E[k] = c.E32[k];
                 f.B[k] = c.B32[k];
             }
-            hipLaunchKernelGGL(k_fenergy<float>, dim3(nblk), dim3(DT), 0, c.st, f, P.nc, c.red);
+            hipLaunchKernelGGL(k_fenergy<float>, dim3(nblk), dim3(DT), 0, c.st, f, P.nc, red);
         }
-        host_sum(c, nblk, 1, fe);
+        reduce_partials(c, red, nblk, 1, 0, fe);
         o->field_energy = 0.5 * fe[0];
     }
     // plasma counts and kinetic energy
@@ -431,15 +484,16 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
         if (c.precision == PIC_FP64_PLAIN) {
             if (c.np_slots > 0) {
                 int nblk = nblocks(c.np_slots, DT);
-                hipLaunchKernelGGL(k_kin, dim3(nblk), dim3(DT), 0, c.st, c.p64, c.np_slots, c.P.mi, c.red);
-                std::vector<double> kp;
-                host_sum(c, nblk, 2, kp);
+                hipLaunchKernelGGL(k_kin, dim3(nblk), dim3(DT), 0, c.st, c.p64, c.np_slots, c.P.mi, red);
+                double kp[2];
+                reduce_partials(c, red, nblk, 2, 0, kp);
                 o->n_plasma = kp[0];
                 o->kin_plasma = kp[1];
             }
         } else {
             double kp[2];
-            split_plasma_kinetic(c, kp);
+            const int nblk = split_plasma_kinetic_partials(c, red);
+            reduce_partials(c, red, nblk, 2, 0, kp);
             o->n_plasma = kp[0];
             o->kin_plasma = kp[1];
         }
@@ -468,7 +522,7 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
                 f.B[k] = c.B64[k];
             }
             hipLaunchKernelGGL(k_gauss<double>, dim3(nblk), dim3(DT), 0, c.st, P, k0r, f, rho, ion, c.rprev, dk,
-                               c.have_rprev, band, c.red);
+                               c.have_rprev, band, red);
             hipLaunchKernelGGL(k_store_r<double>, dim3(nblk), dim3(DT), 0, c.st, P, k0r, f, rho, ion, c.rprev, band);
         } else {
             FieldsT<float> f;
@@ -477,23 +531,16 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
                 f.B[k] = c.B32[k];
             }
             hipLaunchKernelGGL(k_gauss<float>, dim3(nblk), dim3(DT), 0, c.st, P, k0r, f, rho, ion, c.rprev, dk,
-                               c.have_rprev, band, c.red);
+                               c.have_rprev, band, red);
             hipLaunchKernelGGL(k_store_r<float>, dim3(nblk), dim3(DT), 0, c.st, P, k0r, f, rho, ion, c.rprev, band);
         }
-        std::vector<double> h((size_t)3 * nblk);
-        hipMemcpyAsync(h.data(), c.red, 24 * (uint64_t)nblk, hipMemcpyDeviceToHost, c.st);
         hipMemsetAsync(rho, 0, 8 * P.nc, c.st);
         hipMemsetAsync(ion, 0, 8 * P.nz, c.st);
-        hipStreamSynchronize(c.st);
-        double mr = 0, mrho = 0, md = 0;
-        for (int b = 0; b < nblk; ++b) {
-            mr = std::max(mr, h[3 * b]);
-            mrho = std::max(mrho, h[3 * b + 1]);
-            md = std::max(md, h[3 * b + 2]);
-        }
-        o->gauss_max = mr;
-        o->rho_max = mrho;
-        o->gauss_drift = c.have_rprev ? md : -1.0;
+        double g[3];
+        reduce_partials(c, red, nblk, 3, 1, g);
+        o->gauss_max = g[0];
+        o->rho_max = g[1];
+        o->gauss_drift = c.have_rprev ? g[2] : -1.0;
         c.have_rprev = 1;
         c.rprev_k0 = c.k0;
     }
@@ -503,6 +550,33 @@ pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *o) {
     if (e != hipSuccess) return hip_check(c, e, "diag");
     o->error_flags = fl;
     return PIC_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free diagnostics
+// The reduction buffer of pic_diag_static: a file-scope device array, one per
+// GPU the library runs on, held until the process ends.  Host code reaches it
+// only through the address hipGetSymbolAddress returns for each device.
+static __device__ __align__(256) double scratch[DIAG_STATIC_DOUBLES];
+static std::mutex g_scratch_mu;
+static double *g_scratch[64];
+
+pic_status static_scratch_setup(Ctx &c) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (c.device < 0 || c.device >= 64) {
+        c.err = "static scratch: device ordinal beyond 63";
+        return PIC_EDEVICE;
+    }
+    if (g_scratch[c.device]) return PIC_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_check(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch");
+    g_scratch[c.device] = (double *)p;
+    return PIC_OK;
+}
+
+double *static_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < 64 ? g_scratch[device] : nullptr;
 }
 
 }  // namespace pic

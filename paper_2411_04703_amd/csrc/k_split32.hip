@@ -71,6 +71,9 @@ struct SplitState {
     float *tabC, *tabS;
     int nslab;             // work queues: slabs of whole bin layers (one per XCD when they divide evenly)
     int32_t *qnext, *qstart;  // per-slab item counters (stride QPAD); slab q's items are [qstart[q], qstart[q + 1])
+    // host copies of a store's bin counts, offsets and prefix (sized once: later reads allocate nothing)
+    std::vector<int32_t> hcnt;
+    std::vector<int64_t> hoff, hpref;
 };
 
 static SplitState &SS(Ctx &c) { return *static_cast<SplitState *>(c.split); }
@@ -1254,6 +1257,9 @@ static Part32 carve32(char *base, int64_t slots) {
 void split_setup(Ctx &c) {
     SplitState *X = new SplitState();
     c.split = X;
+    X->hcnt.resize(c.P.nbins);
+    X->hoff.resize(c.P.nbins + 1);
+    X->hpref.resize(c.P.nbins + 2);
     const Params &P = c.P;
     char *A = c.arena;
     int64_t nb = P.nbins;
@@ -1919,8 +1925,8 @@ static int64_t split_prefix(Ctx &c, int sp, int32_t &ovf_n) {
     int64_t nb = c.P.nbins;
     Store &s = X.s[sp];
     int cur = c.cur32;
-    std::vector<int32_t> h(nb);
-    std::vector<int64_t> off(nb + 1), pref(nb + 2);
+    std::vector<int32_t> &h = X.hcnt;
+    std::vector<int64_t> &off = X.hoff, &pref = X.hpref;
     (void)hipMemcpyAsync(h.data(), s.cnt[cur], 4 * nb, hipMemcpyDeviceToHost, c.st);
     (void)hipMemcpyAsync(off.data(), s.off[cur], 8 * (nb + 1), hipMemcpyDeviceToHost, c.st);
     (void)hipMemcpyAsync(&ovf_n, s.ovf[cur], 4, hipMemcpyDeviceToHost, c.st);
@@ -2053,7 +2059,8 @@ void split_probe(Ctx &c, double *acc) {
                        acc);
 }
 
-void split_plasma_kinetic(Ctx &c, double *out2) {
+// plasma count and kinetic energy: one pair of partials per bin (and the overflow tail) into red
+int split_plasma_kinetic_partials(Ctx &c, double *red) {
     SplitState &X = SS(c);
     int cur = c.cur32;
     Store &s = X.s[1];
@@ -2063,15 +2070,8 @@ void split_plasma_kinetic(Ctx &c, double *out2) {
     ovf_n = (int32_t)std::min<int64_t>(ovf_n, s.ovf_cap);
     int nblk = c.P.nbins + 1;
     hipLaunchKernelGGL(k_split_kin, dim3(nblk), dim3(256), 0, c.st, c.P, s.buf[cur], s.off[cur], s.cnt[cur],
-                       s.bin_slots, ovf_n, c.P.nbins, c.red);
-    std::vector<double> h(2 * (size_t)nblk);
-    (void)hipMemcpyAsync(h.data(), c.red, 16 * (uint64_t)nblk, hipMemcpyDeviceToHost, c.st);
-    (void)hipStreamSynchronize(c.st);
-    out2[0] = out2[1] = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-        out2[0] += h[2 * b];
-        out2[1] += h[2 * b + 1];
-    }
+                       s.bin_slots, ovf_n, c.P.nbins, red);
+    return nblk;
 }
 
 }  // namespace pic

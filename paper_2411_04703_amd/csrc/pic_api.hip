@@ -510,6 +510,11 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
     c->cap_p = pl.cap_p;
     c->k_bunch_default = pl.d.k_bunch;
     hipGetDevice(&c->device);
+    if (static_scratch_setup(*c) != PIC_OK) {  // the device address of pic_diag_static's array, once per device
+        fprintf(stderr, "pic_init: %s\n", c->err.c_str());
+        delete c;
+        return PIC_EDEVICE;
+    }
     const Params &P = c->P;
     char *A = c->arena;
     uint64_t *off = pl.off;
@@ -737,7 +742,33 @@ pic_status pic_diag(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_di
     pic_status s = pic_sync(c);
     if (s != PIC_OK) return s;
     double kb = bunch_period_cells > 0 ? 2.0 * kPi / bunch_period_cells : c->k_bunch_default;
-    return run_diag(*c, mask, kb, out);
+    return run_diag(*c, mask, kb, out, c->red, c->red_cap);
+}
+
+pic_status pic_diag_static(pic_ctx *c, uint32_t mask, double bunch_period_cells, pic_diag_out *out) {
+    if (!c || !out) return PIC_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device) {
+        c->err = "pic_diag_static: the context's device must be current";
+        return PIC_EINVAL;
+    }
+    double *red = static_scratch(c->device);
+    if (!red) {
+        c->err = "pic_diag_static: no static scratch on this device";
+        return PIC_EDEVICE;
+    }
+    const int64_t need = diag_partials(*c, mask);
+    if (need > DIAG_STATIC_DOUBLES) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "pic_diag_static: %lld partial sums exceed the static scratch of %lld doubles",
+                 (long long)need, (long long)DIAG_STATIC_DOUBLES);
+        c->err = msg;
+        return PIC_ERANGE;
+    }
+    pic_status s = pic_sync(c);
+    if (s != PIC_OK) return s;
+    double kb = bunch_period_cells > 0 ? 2.0 * kPi / bunch_period_cells : c->k_bunch_default;
+    return run_diag(*c, mask, kb, out, red, DIAG_STATIC_DOUBLES);
 }
 
 // copy logical planes of a field into dst (double), un-rotating the ring

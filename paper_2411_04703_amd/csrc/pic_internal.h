@@ -143,7 +143,12 @@ void split_probe(Ctx &c, double *acc);  // lab-frame probe over the binned beam
 void split_lab_groups(Ctx &c, const LabGroupSpec &G, double t, double *out);  // lab-frame groups of the binned beam
 
 // diagnostics (k_diag.hip)
-pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *out);
+int64_t diag_partials(const Ctx &c, uint32_t mask);  // partial sums run_diag needs for this mask
+pic_status run_diag(Ctx &c, uint32_t mask, double kb, pic_diag_out *out, double *red, int64_t red_cap);
+// allocation-free diagnostics: a static device array of DIAG_STATIC_DOUBLES per GPU
+enum : int64_t { DIAG_STATIC_DOUBLES = (int64_t)1 << 19 };  // 4 MiB
+pic_status static_scratch_setup(Ctx &c);  // once per device, with the device current (pic_init)
+double *static_scratch(int device);       // its device address, or NULL before the set-up
 void beam_rho(Ctx &c, double *rho);  // beam charge on the nodes (ring order), added into rho
 void probe_step(Ctx &c);             // lab-frame probe: sample the beam particles that crossed its lab time
 pic_status lab_beam(Ctx &c, double *out, int64_t *n);                   // the beam's lab phase space (8 rows)

@@ -101,9 +101,13 @@ class Sim:
     def sync(self):
         _check(self.L, self.ctx, self.L.pic_sync(self.ctx), "pic_sync")
 
-    def diag(self, mask=abi.PIC_DIAG_MOMENTS | abi.PIC_DIAG_BUNCHING | abi.PIC_DIAG_ENERGY, bunch_period=20.0) -> dict:
+    def diag(self, mask=abi.PIC_DIAG_MOMENTS | abi.PIC_DIAG_BUNCHING | abi.PIC_DIAG_ENERGY, bunch_period=20.0,
+             static=False) -> dict:
+        """Diagnostics; static=True takes the allocation-free entry point (pic_diag_static)."""
         out = abi.pic_diag_out()
-        _check(self.L, self.ctx, self.L.pic_diag(self.ctx, mask, float(bunch_period), C.byref(out)), "pic_diag")
+        f = self.L.pic_diag_static if static else self.L.pic_diag
+        _check(self.L, self.ctx, f(self.ctx, mask, float(bunch_period), C.byref(out)),
+               "pic_diag_static" if static else "pic_diag")
         return out.as_dict()
 
     def read(self, which) -> torch.Tensor:
