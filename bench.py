@@ -297,6 +297,7 @@ def main():
     from paper_2411_04703_amd.sim import derive
     tile_used = derive(w, precision=abi.PIC_FP32_SPLIT, tile=tile)["tile"] if prec == abi.PIC_FP32_SPLIT else None
     wall, ms, launches, n_active, dlast = run(prec)
+    print(f"bench: {args.precision} run done, {wall / args.steps * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
     steps = args.steps
     ps = n_active * steps / wall
     fdtd_ms = ms[1] / steps
@@ -338,6 +339,7 @@ def main():
     }
     if not args.no_fp64 and prec != abi.PIC_FP64_PLAIN:
         w64, ms64, _, na64, d64 = run(abi.PIC_FP64_PLAIN)
+        print(f"bench: fp64 run done, {w64 / steps * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
         ps64 = na64 * steps / w64
         out["fp64_particle_steps_per_s"] = ps64
         out["fp64_ms_per_step"] = w64 / steps * 1e3
