@@ -821,34 +821,43 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
     // (t0x - 1 + a, t0y - 1 + b, t0z - 1 + c)) and its undulator phase table, loaded straight
     // into LDS; nothing waits for them until the next barrier at the top of the item loop
     auto stage = [&](const ItemT &I) {
-        constexpr int NFI = (G::NF + SST - 1) / SST, NEI = (G::NE + SST - 1) / SST;
-        const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+        // thread t owns one (x, y) column of the E box or of the B box: its global offset is
+        // formed once, each plane adds a wave-uniform plane base.  The E columns take the
+        // first threads, the B columns the waves after them and, for what is left, the first
+        // threads again, so that in every wave the lanes that load are a prefix and lane L of
+        // the wave that starts at column c0 writes column c0 + L of a plane
+        constexpr int NCE = G::FX * G::FY, NCB = G::EX * G::EY, WE = (NCE + 63) & ~63;
+        constexpr int NB1 = NCB < SST - WE ? NCB : SST - WE, NB2 = NCB - NB1;
+        static_assert(NCE <= SST && NB2 <= SST, "one pass of columns per box");
+        const int w64 = __builtin_amdgcn_readfirstlane(tid & ~63);
+        const uint32_t pl = (uint32_t)P.nx * (uint32_t)P.ny;
+        auto plane_of = [&](int c) {
+            int l = I.t0z - 1 + c;
+            l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
+            return pl * (uint32_t)ring_plane(l, S.k0r, P.nz);
+        };
+        if (tid < NCE) {
+            const int b = tid / G::FX, a = tid - b * G::FX;
+            const uint32_t col = near_cell32<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, 0);
 #pragma unroll
-        for (int r = 0; r < NFI; ++r) {
-            int k = tid + r * SST;
-            opaque(k);
-            if (k < G::NF) {
-                const int bc = k / G::FX, a = k - bc * G::FX, c = bc / G::FY, b = bc - c * G::FY;
-                int l = I.t0z - 1 + c;
-                l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);  // outside the window: never gathered
-                const uint32_t o = near_cell32<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+            for (int c = 0; c < G::FZ; ++c) {
+                const uint32_t o = col + plane_of(c);
 #pragma unroll
-                for (int qq = 0; qq < 3; ++qq) lds_load(F6[qq] + o, Fs + qq * G::NF + r * SST + wbase);
+                for (int qq = 0; qq < 3; ++qq) lds_load(F6[qq] + o, Fs + qq * G::NF + c * NCE + w64);
             }
         }
+        auto stage_b = [&](int u, int c0) {  // B column u; the wave's first lane has column c0
+            const int b = u / G::EX, a = u - b * G::EX;
+            const uint32_t col = near_cell32<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, 0);
 #pragma unroll
-        for (int r = 0; r < NEI; ++r) {
-            int k = tid + r * SST;
-            opaque(k);
-            if (k < G::NE) {
-                const int bc = k / G::EX, a = k - bc * G::EX, c = bc / G::EY, b = bc - c * G::EY;
-                int l = I.t0z - 1 + c;
-                l = l < 0 ? 0 : (l >= P.nz ? P.nz - 1 : l);
-                const uint32_t o = near_cell32<TY == 1>(P, I.t0x - 1 + a, I.t0y - 1 + b, ring_plane(l, S.k0r, P.nz));
+            for (int c = 0; c < G::EZ; ++c) {
+                const uint32_t o = col + plane_of(c);
 #pragma unroll
-                for (int qq = 0; qq < 3; ++qq) lds_load(F6[3 + qq] + o, Bs + qq * G::NE + r * SST + wbase);
+                for (int qq = 0; qq < 3; ++qq) lds_load(F6[3 + qq] + o, Bs + qq * G::NE + c * NCB + c0);
             }
-        }
+        };
+        if (tid >= WE && tid - WE < NB1) stage_b(tid - WE, w64 - WE);
+        if (NB2 > 0 && tid < NB2) stage_b(NB1 + tid, NB1 + w64);
         static_assert(G::NTAB <= SST, "one table entry per thread");
         if (P.und_kind && tid < G::NTAB) {  // planes t0z - 1 ...: table entries t0z ...
             int k = tid;
