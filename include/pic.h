@@ -129,7 +129,10 @@ typedef struct {
  *            fixed-point current, particles binned by cell tile).
  * pusher: PIC_BORIS, PIC_VAY or PIC_PUSHER_AUTO (Vay when an undulator is on).
  * fp64_gamma_threshold: FP32 mode pushes particles above this Lorentz factor in FP64.
- * fixed_point_frac_bits: 0 = automatic from the peak current bound.
+ * fixed_point_frac_bits: 0 = automatic from the peak current bound (room for 64 times
+ *              the peak density: within 2^62 in FP64 mode, within 2^47 in FP32 mode,
+ *              whose per-tile LDS sums are 48-bit); a larger value than the FP32
+ *              mode's bound returns PIC_ERANGE.
  * check_every: FP32 mode re-lays out its bins when needed, checked every this
  *              many steps (a host synchronisation); 0 = 64.
  * tile: cell tile of the FP32 binned kernels, one of 8x8x4, 8x8x8, 8x8x16, 16x8x4,

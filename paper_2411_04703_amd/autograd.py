@@ -27,7 +27,7 @@ from .sim import Sim
 
 class BunchingLoss(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, K, n0, w, normals, nsteps, every, bunch_period, precision):
+    def forward(ctx, K, n0, w, normals, nsteps, every, bunch_period, precision, init_hook=None):
         w2 = copy.deepcopy(w)
         w2["undulator"]["K"] = float(K)
         w2["plasma"]["n0_lab_cm3"] = float(n0)
@@ -35,6 +35,8 @@ class BunchingLoss(torch.autograd.Function):
         fp64 = Sim(w2, normals, precision=abi.PIC_FP64_PLAIN, record=1, max_steps=nsteps + 2)
         sim = fp64 if precision == abi.PIC_FP64_PLAIN else Sim(w2, normals, precision=abi.PIC_FP32_SPLIT, record=1,
                                                                   max_steps=nsteps + 2)
+        if init_hook is not None:
+            init_hook(sim)
         ckpts = []
         for n in range(nsteps):
             if n % every == 0:
@@ -72,18 +74,21 @@ class BunchingLoss(torch.autograd.Function):
         dn = grad[1] / ctx.n0 * g if ctx.n0 != 0 else 0.0
         ctx.log_grads = grad.copy()
         return (torch.tensor(dK, dtype=torch.float64), torch.tensor(dn, dtype=torch.float64),
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
-def bunching_loss(K, n0, w, normals, nsteps, every=50, bunch_period=20.0, precision=abi.PIC_FP64_PLAIN):
-    """L = |b(2 pi / bunch_period)| after nsteps; differentiable in K and n0 (torch scalars)."""
-    return BunchingLoss.apply(K, n0, w, normals, nsteps, every, bunch_period, precision)
+def bunching_loss(K, n0, w, normals, nsteps, every=50, bunch_period=20.0, precision=abi.PIC_FP64_PLAIN,
+                  init_hook=None):
+    """L = |b(2 pi / bunch_period)| after nsteps; differentiable in K and n0 (torch scalars).
+    init_hook(sim), if given, is applied to the forward simulation before its first step (to
+    perturb its initial particles, say); the gradient is the perturbed run's."""
+    return BunchingLoss.apply(K, n0, w, normals, nsteps, every, bunch_period, precision, init_hook)
 
 
-def bunching_grad(w, normals, nsteps, every=50, bunch_period=20.0, precision=abi.PIC_FP64_PLAIN):
+def bunching_grad(w, normals, nsteps, every=50, bunch_period=20.0, precision=abi.PIC_FP64_PLAIN, init_hook=None):
     """(L, K dL/dK, n0 dL/dn0) for the workload's own K and n0."""
     K = torch.tensor(w["undulator"]["K"], dtype=torch.float64, requires_grad=True)
     n0 = torch.tensor(w["plasma"]["n0_lab_cm3"], dtype=torch.float64, requires_grad=True)
-    L = bunching_loss(K, n0, w, normals, nsteps, every, bunch_period, precision)
+    L = bunching_loss(K, n0, w, normals, nsteps, every, bunch_period, precision, init_hook)
     L.backward()
     return float(L.detach()), float(K.grad) * w["undulator"]["K"], float(n0.grad) * w["plasma"]["n0_lab_cm3"]

@@ -306,6 +306,17 @@ __device__ inline long long to_fixed(double x, double y) {
     return __double_as_longlong(fma(x, y, magic)) - __double_as_longlong(magic);
 }
 
+// the same integer v with the 1.5 * 2^52 left in: the bit pattern 0x4338000000000000 + v.  The
+// bias has its low 48 bits zero, so a sum of such patterns (wrapping modulo 2^64) differs from the
+// sum of the v in bits 48 and up only: sign-extending its low 48 bits gives the sum of the v
+// whenever that lies in [-2^47, 2^47) (the LDS current boxes, whose sums the fixed-point scale of
+// the FP32 mode keeps below 2^47; see unbias48)
+template <bool BIASED> __device__ inline long long to_fixed_as(double x, double y) {
+    if (!BIASED) return to_fixed(x, y);
+    return __double_as_longlong(fma(x, y, 6755399441055744.0));
+}
+__device__ inline long long unbias48(long long sum) { return (long long)((unsigned long long)sum << 16) >> 16; }
+
 // Every Esirkepov contribution of a particle is f P_c[m] A_c[a][b] with
 // |P_c| <= 1 and 0 <= A_c <= 9/16, so |f| bounds them all: one range check per
 // particle (false also for a non-finite f)
@@ -436,13 +447,13 @@ __device__ inline void esk_setup(const float X0[3], const float X1[3], Esk &e) {
 // differently from J_y and the beam's sigma_x drifted from sigma_y by 1e-3 over
 // a 1000-step plasma run).  f = w / dt is formed in FP64; f P_c[m] 2^fs is one
 // FP64 product, and each value converted is that product times A_c rounded
-// once to the fixed point.
+// once to the fixed point (BIASED: left biased, see to_fixed_as).
 // DEP 0 visits nonzero contributions only (one branch each); DEP 1 visits all
 // 48 of a component that moves along its axis; DEP 2 leaves out the window's
 // last node along an axis (m = 2, a = 3 or b = 3) when no lane of the wave
 // crosses there (wave-uniform branches).  The values visited differ only by
 // zeros, so the integer current sums are the same.
-template <int C, int DEP, typename F>
+template <int C, int DEP, bool BIASED, typename F>
 __device__ inline void esk_component(const Esk &e, double f, double fscale, F &&fn) {
     constexpr int CA = C == 2 ? 0 : C + 1, CB = C == 0 ? 2 : C - 1;
     float Pm[3];
@@ -476,9 +487,9 @@ __device__ inline void esk_component(const Esk &e, double f, double fscale, F &&
             for (int b = 0; b < 4; ++b) {
                 if (b == 3 && !b3) break;
                 const double A = (double)Aab(a, b);
-                fn(C, 0, a, b, to_fixed(A, Pd[0]));
-                fn(C, 1, a, b, to_fixed(A, Pd[1]));
-                if (m2) fn(C, 2, a, b, to_fixed(A, Pd[2]));
+                fn(C, 0, a, b, to_fixed_as<BIASED>(A, Pd[0]));
+                fn(C, 1, a, b, to_fixed_as<BIASED>(A, Pd[1]));
+                if (m2) fn(C, 2, a, b, to_fixed_as<BIASED>(A, Pd[2]));
             }
         }
         return;
@@ -492,16 +503,17 @@ __device__ inline void esk_component(const Esk &e, double f, double fscale, F &&
             const double Ad = (double)A;
 #pragma unroll
             for (int m = 0; m < 3; ++m)
-                if (DEP != 0 || Pm[m] != 0.0f) fn(C, m, a, b, to_fixed(Ad, Pd[m]));
+                if (DEP != 0 || Pm[m] != 0.0f) fn(C, m, a, b, to_fixed_as<BIASED>(Ad, Pd[m]));
         }
 }
 
-template <int DEP, typename F> __device__ inline void esk_visit(const Esk &e, double f, double fscale, F &&fn) {
-    esk_component<0, DEP>(e, f, fscale, fn);
+template <int DEP, bool BIASED = false, typename F>
+__device__ inline void esk_visit(const Esk &e, double f, double fscale, F &&fn) {
+    esk_component<0, DEP, BIASED>(e, f, fscale, fn);
     __builtin_amdgcn_sched_barrier(0);
-    esk_component<1, DEP>(e, f, fscale, fn);
+    esk_component<1, DEP, BIASED>(e, f, fscale, fn);
     __builtin_amdgcn_sched_barrier(0);
-    esk_component<2, DEP>(e, f, fscale, fn);
+    esk_component<2, DEP, BIASED>(e, f, fscale, fn);
 }
 
 // carry new offsets into the cell, apply the window shift; false if the particle left the band.
@@ -960,11 +972,12 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                     Esk e;
                     esk_setup(X0, X1, e);
                     // LDS current boxes, origin t0 - 2: box index of offset r is l + r + 2;
-                    // one base index per component, the node offsets are immediates
+                    // one base index per component, the node offsets are immediates; the values
+                    // are added biased (to_fixed_as) and unbiased when the flush reads the sums
                     const int bx = li + e.base[0] + 2, by = lj + e.base[1] + 2, bz = lk + e.base[2] + 2;
                     const int jb[3] = {bx + G::XX * (by + G::XY * bz), G::NJX + bx + G::YX * (by + G::YY * bz),
                                        G::NJX + G::NJY + bx + G::ZX * (by + G::ZY * bz)};
-                    esk_visit<DEP>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
+                    esk_visit<DEP, true>(e, fq, P.fscale, [&](int c, int m, int a, int b, long long iv) {
                         int off;
                         if (c == 0)  // (m, a, b) along (x, y, z)
                             off = m + G::XX * (a + G::XY * b);
@@ -998,7 +1011,7 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
                     load_raw(iop.s[I.sp].in, I.b0 + I.start + tid, nx, REC ? iop.id[I.sp].in : nullptr);
             }
         }
-        // flush nonzero LDS currents with global 64-bit integer atomics, clearing the boxes.
+        // flush nonzero LDS currents (unbiased) with global 64-bit integer atomics, clearing the boxes.
         // Thread t takes columns t and t + SST of the three boxes' (x, y) footprints and walks
         // their planes: a column's global offset is formed once, a plane's is wave-uniform.
         if (C.bin >= 0) {
@@ -1031,9 +1044,11 @@ __global__ void __launch_bounds__(SST, 3) k_split_step(Params P, StepCtx S, cons
 #pragma unroll 1
                     for (int z = 0; z < NPMAX; ++z) {
                         if (z >= np) continue;
-                        const long long v = Js[lb + z * stride];
-                        if (v == 0) continue;
+                        const long long sum = Js[lb + z * stride];
+                        if (sum == 0) continue;
                         Js[lb + z * stride] = 0;
+                        const long long v = unbias48(sum);
+                        if (v == 0) continue;
                         const int l = C.t0z - 2 + z;
                         if (l < 0 || l >= P.nz) continue;  // cannot hold a contribution: particles stay in [3, nz-4)
                         const uint32_t o = col + pl * (uint32_t)ring_plane(l, S.k0r, P.nz);

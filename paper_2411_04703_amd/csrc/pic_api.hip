@@ -25,7 +25,7 @@ pic_status hip_check(Ctx &c, hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? PIC_ENOMEM : PIC_EDEVICE;
 }
 
-static pic_status fail(std::string *err, pic_status s, const char *msg) {
+static pic_status fail(std::string *err, pic_status s, const std::string &msg) {
     if (err) *err = msg;
     return s;
 }
@@ -133,9 +133,17 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     // a single contribution is at most w / dt: FP32 mode converts it exactly while below 2^51
     double vmax = 2.0 * std::max(P.wsheet, P.wbeam) / P.dt + 1e-6;
     int fb = o->fixed_point_frac_bits;
-    if (fb == 0) fb = std::min(62 - (int)ceil(log2(64.0 * jb)), 51 - (int)ceil(log2(vmax)));
+    // the FP32 mode's LDS tiles hold their sums in 48 bits (biased adds): 64 times the peak density
+    // within 2^47 instead of 2^62, a quantum still far below the FP32 rounding of the contributions
+    const int fb_tile = 47 - (int)ceil(log2(64.0 * jb));
+    const bool split = o->precision == PIC_FP32_SPLIT;
+    if (fb == 0) fb = std::min(split ? fb_tile : 62 - (int)ceil(log2(64.0 * jb)), 51 - (int)ceil(log2(vmax)));
     fb = std::min(56, std::max(20, fb));
     if (o->fixed_point_frac_bits > 60) return fail(err, PIC_ERANGE, "options: fixed_point_frac_bits > 60");
+    if (split && fb > fb_tile)
+        return fail(err, PIC_ERANGE,
+                    "options: FP32 mode fixed point needs frac_bits <= " + std::to_string(fb_tile) +
+                        " for this peak density (48-bit tile sums)");
     P.frac_bits = fb;
     P.fscale = ldexp(1.0, fb);
     P.finv = ldexp(1.0, -fb);

@@ -141,6 +141,23 @@ def test_frac_bits_range_error():
     assert e.value.status == abi.PIC_ERANGE
 
 
+def test_fp32_mode_fixed_point_leaves_room_for_48_bit_tile_sums():
+    """The FP32 mode sums a tile's current contributions in LDS with the FMA rounding bias left in,
+    which keeps only 48 bits of the sum: its fixed-point scale leaves 64 times the peak density
+    below 2^47 (the FP64 mode's below 2^62), and a requested scale beyond that is refused."""
+    for k in range(6):
+        w = pin.workload(k)
+        f32 = sim.derive(w, precision=abi.PIC_FP32_SPLIT)["frac_bits"]
+        f64 = sim.derive(w, precision=abi.PIC_FP64_PLAIN)["frac_bits"]
+        assert 20 <= f32 <= f64
+    fb = sim.derive(pin.workload(1), precision=abi.PIC_FP32_SPLIT)["frac_bits"]
+    assert sim.query_layout(pin.workload(1), precision=abi.PIC_FP32_SPLIT, frac_bits=fb).arena_bytes > 0
+    with pytest.raises(abi.PicError) as e:
+        sim.query_layout(pin.workload(1), precision=abi.PIC_FP32_SPLIT, frac_bits=fb + 1)
+    assert e.value.status == abi.PIC_ERANGE
+    assert sim.query_layout(pin.workload(1), precision=abi.PIC_FP64_PLAIN, frac_bits=fb + 1).arena_bytes > 0
+
+
 def test_gpu_entry_points_fail_loudly_without_device():
     import torch
     if torch.cuda.is_available():

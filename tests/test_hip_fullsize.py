@@ -260,26 +260,40 @@ def test_workload1_stays_stable_over_two_and_a_half_runs():
     assert s.diag()["n_beam"] > 0.98 * W["beam"]["n_macro"]
 
 
+@pytest.mark.timeout(900)
 def test_workload1_front_face_changes_no_result():
     """The moving window's front face holds the tangential E at zero.  Over the workload's 1000
-    steps the same beam and plasma in a window that reaches 64 cells further ahead (same particles,
-    same distance from the back face) end with the same beam diagnostics: the FP32 path is
-    deterministic, so any difference is the face's doing.  The beam-plasma run amplifies any
-    rounding-level difference a thousandfold and more (four FP64 runs whose particles differ by
-    one FP32 ulp end 1e-5 to 4e-4 apart in these moments), so the bar is what no result of the
-    FP32 path could resolve: a tenth of its full-run tolerance (measured: 4e-6)."""
+    steps, sampled every 100, the tangential E of the five planes behind the face stays below 1e-6
+    of the field's peak in both paths (measured: 3e-14 in FP64, 0 in FP32), and the FP64 path in a
+    window that reaches 64 cells further ahead (same particles, same distance from the back face)
+    ends with the same beam moments to 1e-6 relative and |b| to 1e-9 absolute (measured: 4e-9 and
+    8e-13).  What the face changes starts in the planes next to it and is carried back with the
+    inflowing plasma; two FP32 runs that differ anywhere by an ulp end 1e-5 to 4e-4 apart in these
+    moments after this beam-plasma run (the spread of the full-run tolerance test), so comparing
+    the FP32 path's two windows would measure that amplification of an ulp, not the face."""
     import copy
     nsteps = W["steps"]
     w2 = copy.deepcopy(W)
     w2["grid"]["nz"] = W["grid"]["nz"] + 64
-    out = []
-    for w in (W, w2):
-        s = _gpu(1, w=w)
-        s.step(nsteps)
-        out.append(s.diag())
-        del s
-    a, b = out
+    diags = []
+    for w, precs in ((W, (0, 1)), (w2, (0,))):
+        nz = w["grid"]["nz"]
+        for prec in precs:
+            s = _gpu(prec, w=w, **({"max_steps": 64} if prec == 0 else {}))
+            worst = 0.0
+            for _ in range(10):
+                s.step(nsteps // 10)
+                E = [s.field(f) for f in ("Ex", "Ey", "Ez")]
+                peak = max(float(np.abs(e).max()) for e in E)
+                near = max(float(np.abs(e[nz - 6:nz - 1]).max()) for e in E[:2])
+                assert near <= 1e-6 * peak, (prec, nz, near, peak)
+                worst = max(worst, near / peak)
+            if prec == 0:
+                diags.append(s.diag())
+            del s
+            print("front face: precision", prec, "nz", nz, "tangential E near the face / peak", worst, flush=True)
+    a, b = diags
     assert a["n_beam"] == b["n_beam"] == W["beam"]["n_macro"]
     for k in ("mean", "sigma", "usigma", "emit"):
-        np.testing.assert_allclose(a[k], b[k], rtol=1e-4, atol=1e-12, err_msg=k)
-    assert abs(a["b1_abs"] - b["b1_abs"]) < 1e-7
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-6, atol=1e-12, err_msg=k)
+    assert abs(a["b1_abs"] - b["b1_abs"]) < 1e-9
