@@ -38,18 +38,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_split_step_128x128x512_hbm_counters
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_04703_amd", "csrc", "k_split32.hip")
 
 
-def measured_traffic():
+def measured_traffic(tile):
     """HBM bytes per launch of the particle kernel from the committed FETCH_SIZE /
     WRITE_SIZE counter runs (calibrated against a plain copy), or None when the
-    kernel source changed since they were taken."""
+    kernel source or the tile changed since they were taken."""
     import hashlib
     try:
         text = open(COUNTERS).read()
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines()
-                if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
-    if len(vals) != 2:
+                if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ", "tile: ")))
+    if len(vals) != 3 or [int(v) for v in vals["tile"].split()] != list(tile):
         return None
     if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != vals["kernel_source_sha256"].strip():
         return None
@@ -327,7 +327,7 @@ def main():
                               "step_events": ms[3] / steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if (prec == abi.PIC_FP32_SPLIT and tile == (0, 0, 0)
+                     "traffic": measured_traffic(tile_used) if (prec == abi.PIC_FP32_SPLIT and tile == (0, 0, 0)
                                                        and args.variant == 0 and args.workload == 1) else None,
                      "measured_copy_GBps": copy["GBps_read_plus_write"],
                      "frac_of_measured_copy": achieved / copy["GBps_read_plus_write"],

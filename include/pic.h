@@ -137,7 +137,7 @@ typedef struct {
  *              many steps (a host synchronisation); 0 = 64.
  * tile: cell tile of the FP32 binned kernels, one of 8x8x4, 8x8x8, 8x8x16, 16x8x4,
  *       16x16x4, 16x8x8, and 16x1x16 for two-dimensional x-z grids (ny = 1)
- *       (edges divide the grid); 0,0,0 = the first of 16x16x4, 16x8x8, 8x8x16,
+ *       (edges divide the grid); 0,0,0 = the first of 16x8x8, 16x16x4, 8x8x16,
  *       8x8x8, 16x8x4, 8x8x4, 16x1x16 that divides the grid.
  * max_steps: sizing of the plasma capacity of the FP64 mode (injection between
  *            compactions, or over the whole run when record = 1).

@@ -150,9 +150,10 @@ static pic_status derive_params(const pic_grid *g, const pic_frame *f, const pic
     if (o->precision == PIC_FP32_SPLIT) {
         int t[3] = {o->tile[0], o->tile[1], o->tile[2]};
         if (!t[0] && !t[1] && !t[2]) {
-            // largest tile (least halo per cell) that divides the grid, by measured speed
-            // (16 x 1 x 16: two-dimensional x-z grids, ny = 1)
-            static const int pref[7][3] = {{16, 16, 4}, {16, 8, 8}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4},
+            // the first tile that divides the grid, in order of measured speed (16 x 8 x 8 is
+            // 1.5-2.7 % faster than 16 x 16 x 4 on the 128x128x512 to 512x512x2048 workloads;
+            // 16 x 1 x 16: two-dimensional x-z grids, ny = 1)
+            static const int pref[7][3] = {{16, 8, 8}, {16, 16, 4}, {8, 8, 16}, {8, 8, 8}, {16, 8, 4}, {8, 8, 4},
                                            {16, 1, 16}};
             for (int k = 0; k < 7; ++k)
                 if (g->nx % pref[k][0] == 0 && g->ny % pref[k][1] == 0 && g->nz % pref[k][2] == 0) {
