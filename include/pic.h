@@ -81,13 +81,22 @@ typedef struct {
  * (longitudinal, boosted-frame cells; the lab rms length follows from Eq. Belon),
  * lab Lorentz factor gamma_lab with relative rms spread, normalised rms emittances
  * emit_n_m (m).  normals: HOST pointer to 6 x n_macro standard-normal draws in
- * rows (x, y, z, ux, uy, energy); read during pic_init only.  The beam centre sits
- * on the box axis, z_center_cells from the window's back face at t' = 0. */
+ * rows (x, y, z, ux, uy, energy), read during pic_init only; or NULL: pic_init
+ * then draws them on the device from seed.  The draw for particle p: two blocks
+ * of the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC 2011), counters
+ * (p mod 2^32, p div 2^32, j, 0) for j = 0, 1 under the key (seed mod 2^32,
+ * seed div 2^32), give eight 32-bit words w0..w7; the pairs (w0, w1), (w2, w3),
+ * (w4, w5) become rows (0, 1), (2, 3), (4, 5) by the Box-Muller transform in
+ * FP64: U = (w + 1/2) 2^-32, n = sqrt(-2 ln U_a) cos(2 pi U_b),
+ * n' = sqrt(-2 ln U_a) sin(2 pi U_b).  The beam centre sits on the box axis,
+ * z_center_cells from the window's back face at t' = 0. */
 typedef struct {
     int64_t n_macro;
     double charge_C, gamma_lab, rel_energy_spread_rms;
     double sigma_cells[3], emit_n_m[2], z_center_cells;
     const double *normals;
+    uint64_t seed;
 } pic_beam;
 
 /* Cold plasma at rest in the lab with lab density n0 (cm^-3) on a regular

@@ -36,7 +36,8 @@ class pic_frame(C.Structure):
 class pic_beam(C.Structure):
     _fields_ = [("n_macro", C.c_int64), ("charge_C", C.c_double), ("gamma_lab", C.c_double),
                 ("rel_energy_spread_rms", C.c_double), ("sigma_cells", C.c_double * 3),
-                ("emit_n_m", C.c_double * 2), ("z_center_cells", C.c_double), ("normals", C.c_void_p)]
+                ("emit_n_m", C.c_double * 2), ("z_center_cells", C.c_double), ("normals", C.c_void_p),
+                ("seed", C.c_uint64)]
 
 
 class pic_plasma(C.Structure):
@@ -151,7 +152,7 @@ class PicError(RuntimeError):
 
 def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHER_AUTO, record=0, max_steps=0,
                           check_every=0, tile=(0, 0, 0), frac_bits=0, gamma_threshold=0.0, stream=None,
-                          normals=None, variant=0, wg_per_cu=0, init_fields=0, neutral_fade_s=0.0):
+                          normals=None, seed=0, variant=0, wg_per_cu=0, init_fields=0, neutral_fade_s=0.0):
     """Fill the C structs from a workload dictionary (plain field copies)."""
     g, fr, b, p, u = w["grid"], w["frame"], w["beam"], w["plasma"], w["undulator"]
     grid = pic_grid(g["nx"], g["ny"], g["nz"], 0, g["dx_m"], g["cfl"])
@@ -165,6 +166,7 @@ def structs_from_workload(w: dict, *, precision=PIC_FP64_PLAIN, pusher=PIC_PUSHE
     beam.emit_n_m[:] = b["emit_n_m"]
     beam.z_center_cells = b["z_center_cells"]
     beam.normals = None if normals is None else normals.ctypes.data
+    beam.seed = int(seed)
     plasma = pic_plasma()
     plasma.n0_lab_cm3 = p["n0_lab_cm3"]
     plasma.ppc[:] = p["ppc"]

@@ -448,6 +448,47 @@ static pic_status step64(Ctx &c) {
     return PIC_OK;
 }
 
+// ---------------------------------------------------------------- beam draws from a seed
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds, each two 32 x 32 -> 64-bit
+// products of counter words with fixed multipliers whose high halves are mixed (xor) with the
+// other two counter words and the key; the key advances by two Weyl constants between rounds.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = (uint32_t)p1;
+        c[2] = n2;
+        c[3] = (uint32_t)p0;
+    }
+}
+
+// the beam's standard normals from the seed, as pic_beam defines them: row r of particle p at
+// out[r n + p] (rows x, y, z, ux, uy, energy), one thread per particle
+__global__ void __launch_bounds__(256) k_beam_normals(uint64_t seed, int64_t n, double *out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t w[8];
+    for (int j = 0; j < 2; ++j) {
+        uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), (uint32_t)j, 0u};
+        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        for (int q = 0; q < 4; ++q) w[4 * j + q] = c[q];
+    }
+    const double two_m32 = 2.3283064365386963e-10;  // 2^-32: U in (0, 1), never 0 or 1
+    for (int r = 0; r < 3; ++r) {
+        const double ua = ((double)w[2 * r] + 0.5) * two_m32, ub = ((double)w[2 * r + 1] + 0.5) * two_m32;
+        const double rad = sqrt(-2.0 * log(ua));
+        double s, co;
+        sincospi(2.0 * ub, &s, &co);  // sin and cos of 2 pi ub
+        out[(2 * r) * n + p] = rad * co;
+        out[(2 * r + 1) * n + p] = rad * s;
+    }
+}
+
 }  // namespace pic
 
 using namespace pic;
@@ -494,10 +535,6 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
         fprintf(stderr, "pic_init: arena missing, misaligned or smaller than %llu bytes\n",
                 (unsigned long long)pl.arena);
         return PIC_ENOMEM;
-    }
-    if (b->n_macro > 0 && !b->normals) {
-        fprintf(stderr, "pic_init: beam.normals is NULL\n");
-        return PIC_EINVAL;
     }
     pic_ctx *c = new pic_ctx();
     c->P = pl.P;
@@ -569,12 +606,18 @@ pic_status pic_init(const pic_grid *g, const pic_frame *f, const pic_beam *b, co
         delete c;
         return PIC_EDEVICE;
     }
-    // beam: normals to the device, FP64 transform
+    // beam: normals to the device (or drawn there from the seed), FP64 transform
     double bw = 0.0;
     if (b->n_macro > 0) {
-        e = hipMemcpyAsync(c->stage, b->normals, 8 * 6 * (uint64_t)b->n_macro, hipMemcpyHostToDevice, c->st);
+        if (b->normals) {
+            e = hipMemcpyAsync(c->stage, b->normals, 8 * 6 * (uint64_t)b->n_macro, hipMemcpyHostToDevice, c->st);
+        } else {
+            hipLaunchKernelGGL(k_beam_normals, dim3(nblocks(b->n_macro, 256)), dim3(256), 0, c->st, b->seed,
+                               b->n_macro, c->stage);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess) {
-            hip_check(*c, e, "normals upload");
+            hip_check(*c, e, b->normals ? "normals upload" : "normals from the seed");
             delete c;
             return PIC_EDEVICE;
         }

@@ -46,18 +46,24 @@ class Sim:
     """A simulation on the current HIP device.
 
     precision: abi.PIC_FP64_PLAIN or abi.PIC_FP32_SPLIT.  normals: (6, n_macro)
-    float64 standard normals the beam is sampled from (host array).
+    float64 standard normals the beam is sampled from (host array), or None: the
+    library draws them on the device from seed (an integer option; see pic_beam).
     """
 
-    def __init__(self, w: dict, normals: np.ndarray, *, device="cuda", stream=None, **opts):
+    def __init__(self, w: dict, normals: np.ndarray | None, *, device="cuda", stream=None, **opts):
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the simulation runs only on the GPU")
         self.L = abi.load()
         self.w = w
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.normals = np.ascontiguousarray(normals, dtype=np.float64)
-        assert self.normals.shape == (6, w["beam"]["n_macro"])
+        if normals is None:
+            if "seed" not in opts:
+                raise ValueError("Sim: give either the beam's normals or a seed to draw them on the device")
+            self.normals = None
+        else:
+            self.normals = np.ascontiguousarray(normals, dtype=np.float64)
+            assert self.normals.shape == (6, w["beam"]["n_macro"])
         structs = abi.structs_from_workload(w, stream=self.stream.cuda_stream, normals=self.normals, **opts)
         self.structs = structs
         lay = abi.pic_layout()
