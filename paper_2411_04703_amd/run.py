@@ -23,6 +23,9 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=100, help="report interval in steps")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--device-draws", action="store_true",
+                    help="draw the beam's normals on the device from --seed (Philox4x32-10 + Box-Muller; no host "
+                         "array, no upload) instead of the host draws the tests and the benchmark use")
     ap.add_argument("--no-gauss", action="store_true", help="skip the FP64 Gauss-law residual (a full-grid pass)")
     ap.add_argument("--init-fields", action="store_true", help="start from the beam's self-field (else zero fields)")
     ap.add_argument("--mobile-ions", type=float, default=None, metavar="MASS",
@@ -48,7 +51,10 @@ def main(argv=None):
     if a.init_fields:
         opts["init_fields"] = 1
     t0 = time.perf_counter()
-    sim = Sim(w, pin.beam_normals(w["beam"]["n_macro"], a.seed), precision=prec, **opts)
+    if a.device_draws:
+        sim = Sim(w, None, precision=prec, seed=a.seed, **opts)
+    else:
+        sim = Sim(w, pin.beam_normals(w["beam"]["n_macro"], a.seed), precision=prec, **opts)
     sim.sync()
     init_s = time.perf_counter() - t0
     mask = abi.PIC_DIAG_MOMENTS | abi.PIC_DIAG_BUNCHING | abi.PIC_DIAG_ENERGY
