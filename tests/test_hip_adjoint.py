@@ -1,8 +1,9 @@
 """GPU adjoint (FP64 record mode, checkpoint and recompute) against central
 finite differences of the GPU forward, h = 1e-6 relative, bar 1e-4 relative:
 on the 16x16x64 subcase at both ends of the parameter ranges (K in [0.5, 2],
-n0 in [1e15, 1e17] cm^-3), and on the 64x64x256 adjoint workload (1,048,576
-beam particles plus 2 ppc plasma, 500 steps, checkpoint every 50)."""
+n0 in [1e15, 1e17] cm^-3; there also at h/10, with the perturbed runs' discrete
+events equal to the unperturbed run's), and on the 64x64x256 adjoint workload
+(1,048,576 beam particles plus 2 ppc plasma, 500 steps, checkpoint every 50)."""
 import copy
 
 import numpy as np
@@ -36,15 +37,40 @@ def _check(w, nrm, nsteps, every):
     return L, gK, gn
 
 
+def _events(w, nrm, nsteps, K, n0):
+    """The discrete events of a forward run: window shifts, plasma entering and leaving, beam losses."""
+    from paper_2411_04703_amd.sim import Sim
+    w2 = copy.deepcopy(w)
+    w2["undulator"]["K"] = K
+    w2["plasma"]["n0_lab_cm3"] = n0
+    s = Sim(w2, nrm, precision=0, max_steps=nsteps + 2)
+    s.step(nsteps)
+    d = s.diag()
+    return d["k0"], d["n_beam"], d["n_plasma"], d["beam_lost"]
+
+
 @pytest.mark.parametrize("K,n0", [(0.5, 1e15), (2.0, 1e17)])
 def test_adjoint_subcase_matches_central_differences(K, n0):
+    """Also: the central differences at h and h/10 agree (neither step size is truncation- or
+    rounding-limited at the bar), and the perturbed forward runs see the same discrete events as the
+    unperturbed one (the loss is differentiable along the differences)."""
     w = pin.adjoint_subcase()
     w["undulator"]["K"] = K
     w["plasma"]["n0_lab_cm3"] = n0
     w["beam"]["charge_C"] = 3e-9
     nrm = pin.beam_normals(w["beam"]["n_macro"], 7)
     w["frame"]["window_beta"] = po.Sim(w, nrm).info().bw
-    _check(w, nrm, 48, 12)
+    nsteps, every = 48, 12
+    L, gK, gn = _check(w, nrm, nsteps, every)
+    h = H / 10
+    fK = (_loss(w, nrm, nsteps, every, K * (1 + h), n0) - _loss(w, nrm, nsteps, every, K * (1 - h), n0)) / (2 * h)
+    fn = (_loss(w, nrm, nsteps, every, K, n0 * (1 + h)) - _loss(w, nrm, nsteps, every, K, n0 * (1 - h))) / (2 * h)
+    assert gK == pytest.approx(fK, rel=1e-4), (gK, fK)
+    assert gn == pytest.approx(fn, rel=1e-4), (gn, fn)
+    base = _events(w, nrm, nsteps, K, n0)
+    assert base[0] > 0 and base[2] > 0, base
+    for KK, nn in ((K * (1 + H), n0), (K * (1 - H), n0), (K, n0 * (1 + H)), (K, n0 * (1 - H))):
+        assert _events(w, nrm, nsteps, KK, nn) == base, (KK, nn)
 
 
 def test_adjoint_workload3_matches_central_differences():
