@@ -20,3 +20,13 @@ def oracle_built():
             and os.path.exists(os.path.join(ROOT, "oracle", "liborc_cs.so"))):
         build.build()
     return True
+
+
+@pytest.fixture
+def progress(capsys):
+    """Print a line past pytest's output capture, at once: long GPU tests report each finished
+    stage (a run of a thousand steps, say), so that a run under -q shows where it is."""
+    def say(*args):
+        with capsys.disabled():
+            print(*args, flush=True)
+    return say

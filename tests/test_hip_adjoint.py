@@ -79,7 +79,7 @@ def test_adjoint_workload3_matches_central_differences():
     _check(w, nrm, w["steps"], w["checkpoint_every"])
 
 
-def test_fp32_mode_adjoint_workload3_matches_fp64_mode_and_differences():
+def test_fp32_mode_adjoint_workload3_matches_fp64_mode_and_differences(progress):
     """FP32 mode on the 64x64x256 adjoint workload (500 steps, checkpoint every 50): the adjoint
     linearised about the FP32 trajectory against the FP64-mode adjoint and central differences of
     the FP64 forward, 1e-3 relative -- the FP32 trajectory departs from the FP64 one by per-step
@@ -92,7 +92,9 @@ def test_fp32_mode_adjoint_workload3_matches_fp64_mode_and_differences():
     n, every = w["steps"], w["checkpoint_every"]
     K, n0 = w["undulator"]["K"], w["plasma"]["n0_lab_cm3"]
     L64, gK64, gn64 = bunching_grad(w, nrm, n, every=every)
+    progress("workload 3: fp64-mode gradient done")
     L32, gK32, gn32 = bunching_grad(w, nrm, n, every=every, precision=abi.PIC_FP32_SPLIT)
+    progress("workload 3: fp32-mode gradient done")
     fK = (_loss(w, nrm, n, every, K * (1 + H), n0) - _loss(w, nrm, n, every, K * (1 - H), n0)) / (2 * H)
     fn = (_loss(w, nrm, n, every, K, n0 * (1 + H)) - _loss(w, nrm, n, every, K, n0 * (1 - H))) / (2 * H)
     print("workload 3 FP32-mode adjoint", L32 / L64 - 1, gK32 / gK64 - 1, gn32 / gn64 - 1, gK32 / fK - 1,

@@ -192,7 +192,7 @@ def _ulp_perturbed(sim, rng):
 
 
 @pytest.mark.timeout(900)
-def test_workload1_full_run_fp32_within_stated_tolerance():
+def test_workload1_full_run_fp32_within_stated_tolerance(progress):
     """After the workload's full 1000 steps the FP32 path's beam moments agree with the FP64
     path's (which follows the oracle to 1e-12 per step at small sizes) within the tolerance stated
     before the measurement: per quantity, max(1e-3 relative, 3x the spread of four FP64 runs
@@ -216,7 +216,7 @@ def test_workload1_full_run_fp32_within_stated_tolerance():
         s.step(nsteps)
         d64p.append(s.diag())
         del s
-        print("fp64 run", seed, "done", flush=True)
+        progress("full-run tolerance: fp64 run", seed, "of 0-4 done")
     d64 = d64p[0]
     assert d32["n_beam"] == d64["n_beam"] and d32["n_plasma"] == d64["n_plasma"]
     report = {}
@@ -261,7 +261,7 @@ def test_workload1_stays_stable_over_two_and_a_half_runs():
 
 
 @pytest.mark.timeout(900)
-def test_workload1_front_face_changes_no_result():
+def test_workload1_front_face_changes_no_result(progress):
     """The moving window's front face holds the tangential E at zero.  Over the workload's 1000
     steps, sampled every 100, the tangential E of the five planes behind the face stays below 1e-6
     of the field's peak in both paths (measured: 3e-14 in FP64, 0 in FP32), and the FP64 path in a
@@ -291,7 +291,7 @@ def test_workload1_front_face_changes_no_result():
             if prec == 0:
                 diags.append(s.diag())
             del s
-            print("front face: precision", prec, "nz", nz, "tangential E near the face / peak", worst, flush=True)
+            progress("front face: precision", prec, "nz", nz, "tangential E near the face / peak", worst)
     a, b = diags
     assert a["n_beam"] == b["n_beam"] == W["beam"]["n_macro"]
     for k in ("mean", "sigma", "usigma", "emit"):
